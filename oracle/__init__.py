@@ -1,0 +1,146 @@
+"""CPU oracle for the star-forest (SF) operations -- TEST INFRASTRUCTURE ONLY.
+
+Plain definitions of SFBcast, SFReduce and SFFetchAndOp (paper Section 3.2),
+written in C (``sf_oracle.c``) and called here through ctypes on NumPy
+arrays.  Only the tests, the package smoke check and the benchmark's CPU
+baseline use this package; the product path never imports it, and it shares
+no code with the GPU library.
+
+Data are NumPy arrays of units: shape ``[n]`` (bs = 1) or ``[n, bs]``, with
+dtype float64 / float32 / int32 / int64, or :data:`PAIR` (the MAXLOC unit
+``{double v; int32 i; int32 pad}``, 16-byte extent).
+
+Every wrapper is functional: it copies its data arguments and returns new
+arrays, so a test can keep the inputs.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+
+PAIR = np.dtype([("v", "<f8"), ("i", "<i4"), ("pad", "<i4")])
+
+# enum values of sf_oracle.h
+_DT = {np.dtype(np.float64): 0, np.dtype(np.float32): 1, np.dtype(np.int32): 2,
+       np.dtype(np.int64): 3, PAIR: 4}
+REPLACE, SUM, MAX, MIN, MAXLOC = 0, 1, 2, 3, 4
+OPS = {"replace": REPLACE, "sum": SUM, "max": MAX, "min": MIN, "maxloc": MAXLOC}
+PW_TOPDOWN, PW_BOTTOMUP = 0, 1
+
+_lib = None
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (no fast-math, no FP contraction)."""
+    src = os.path.join(_HERE, "sf_oracle.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _SO + ".tmp", src, "-lm"]
+    if force or not os.path.exists(_SO):
+        subprocess.check_call(cmd)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        i64, p, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        L.orc_bcast.argtypes = [i64, i64, p, p, ci, ci, ci, p, p]
+        L.orc_reduce.argtypes = [i64, i64, p, p, ci, ci, ci, p, p, ci]
+        L.orc_fetch_and_op.argtypes = [i64, i64, p, p, ci, ci, ci, p, p, p]
+        for f in (L.orc_bcast, L.orc_reduce, L.orc_fetch_and_op):
+            f.restype = ci
+        L.orc_pairwise_f64.argtypes = [p, i64, ci]
+        L.orc_pairwise_f64.restype = ctypes.c_double
+        L.orc_pairwise_f32.argtypes = [p, i64, ci]
+        L.orc_pairwise_f32.restype = ctypes.c_float
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _graph(nroots, iroot, ilocal):
+    iroot = np.ascontiguousarray(iroot, dtype=np.int64)
+    ilocal = None if ilocal is None else np.ascontiguousarray(ilocal, dtype=np.int64)
+    if ilocal is not None and ilocal.shape != iroot.shape:
+        raise ValueError("ilocal and iroot differ in length")
+    return int(nroots), iroot, ilocal
+
+
+def _unit(a):
+    a = np.asarray(a)
+    if a.dtype not in _DT:
+        raise TypeError(f"unsupported unit dtype {a.dtype}")
+    bs = 1 if a.ndim == 1 else int(np.prod(a.shape[1:]))
+    return _DT[a.dtype], bs
+
+
+def _op(op):
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def bcast(nroots, iroot, ilocal, rootdata, leafdata, op="replace"):
+    """Return a copy of ``leafdata`` after SFBcast(rootdata -> leafdata, op)."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    root = np.ascontiguousarray(rootdata)
+    leaf = np.array(leafdata, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) and root.shape[0] == nroots
+    if iroot.size and (ilocal.max() if ilocal is not None else iroot.size - 1) >= leaf.shape[0]:
+        raise ValueError("leaf buffer smaller than the leaf space")
+    rc = lib().orc_bcast(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                         _ptr(root), _ptr(leaf))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return leaf
+
+
+def reduce(nroots, iroot, ilocal, leafdata, rootdata, op="sum", pw_form=PW_TOPDOWN):
+    """Return a copy of ``rootdata`` after SFReduce(leafdata -> rootdata, op)."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    leaf = np.ascontiguousarray(leafdata)
+    root = np.array(rootdata, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) and root.shape[0] == nroots
+    if iroot.size and (ilocal.max() if ilocal is not None else iroot.size - 1) >= leaf.shape[0]:
+        raise ValueError("leaf buffer smaller than the leaf space")
+    rc = lib().orc_reduce(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                          _ptr(leaf), _ptr(root), pw_form)
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return root
+
+
+def fetch_and_op(nroots, iroot, ilocal, rootdata, leafdata, leafupdate, op="sum"):
+    """Return (root, leafupdate) after SFFetchAndOp in leaf order."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    leaf = np.ascontiguousarray(leafdata)
+    root = np.array(rootdata, copy=True, order="C")
+    upd = np.array(leafupdate, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) == _unit(upd) and root.shape[0] == nroots
+    rc = lib().orc_fetch_and_op(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                                _ptr(root), _ptr(leaf), _ptr(upd))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return root, upd
+
+
+def pairwise(x, form=PW_TOPDOWN):
+    """Canonical pairwise sum of a 1-D float64/float32 array."""
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.float64:
+        return np.float64(lib().orc_pairwise_f64(_ptr(x), x.size, form))
+    if x.dtype == np.float32:
+        return np.float32(lib().orc_pairwise_f32(_ptr(x), x.size, form))
+    raise TypeError(x.dtype)

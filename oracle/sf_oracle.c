@@ -1,0 +1,296 @@
+/*
+ * sf_oracle.c -- plain, slow, obviously correct CPU definitions of SFBcast,
+ * SFReduce and SFFetchAndOp (paper Section 3.2).  TEST INFRASTRUCTURE ONLY:
+ * used by the tests, the package smoke check and the benchmark's CPU
+ * baseline, never by the product path.  See sf_oracle.h for the contract.
+ *
+ * Readings of points the paper leaves open (each is also listed with the
+ * design notes of the project):
+ *  - the root takes part in every Reduce as an operand (Section 4.1: the
+ *    transpose product adds leaf contributions back onto y);
+ *  - FP SUM order: canonical pairwise sum over the root's leaves in ascending
+ *    leaf index, then root + T with the root as the left operand;
+ *  - MAX/MIN compare under a total order in which -0 < +0;
+ *  - MAXLOC: larger value wins, ties go to the smaller index (MPI rule);
+ *  - Reduce REPLACE with several leaves: the last leaf in leaf order wins;
+ *  - integer SUM wraps around (computed in unsigned arithmetic);
+ *  - Bcast with op != REPLACE: leaf = op(leaf, root), leaf on the left.
+ */
+#include "sf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  double v;
+  int32_t i;
+  int32_t pad;
+} orc_pair;
+
+/* ---------------------------------------------------------------- helpers */
+
+static int64_t elem_size(int dtype) {
+  switch (dtype) {
+    case ORC_F64: return 8;
+    case ORC_F32: return 4;
+    case ORC_I32: return 4;
+    case ORC_I64: return 8;
+    case ORC_PAIR: return 16;
+    default: return -1;
+  }
+}
+
+/* Total order on doubles with -0 < +0 (no NaN in the inputs). */
+static int less_f64(double a, double b) {
+  if (a < b) return 1;
+  if (a > b) return 0;
+  return signbit(a) && !signbit(b);
+}
+static int less_f32(float a, float b) {
+  if (a < b) return 1;
+  if (a > b) return 0;
+  return signbit(a) && !signbit(b);
+}
+
+/* MAXLOC: is a strictly better than b? */
+static int pair_better(const orc_pair *a, const orc_pair *b) {
+  if (less_f64(b->v, a->v)) return 1;
+  if (less_f64(a->v, b->v)) return 0;
+  return a->i < b->i;
+}
+
+/* dst = op(dst, src) for one element; dst is the left operand. */
+static void apply_op(int dtype, int op, void *dst, const void *src) {
+  if (op == ORC_REPLACE) {
+    if (dtype == ORC_PAIR) {
+      ((orc_pair *)dst)->v = ((const orc_pair *)src)->v;
+      ((orc_pair *)dst)->i = ((const orc_pair *)src)->i;
+    } else {
+      memcpy(dst, src, (size_t)elem_size(dtype));
+    }
+    return;
+  }
+  switch (dtype) {
+    case ORC_F64: {
+      double a = *(double *)dst, b = *(const double *)src;
+      if (op == ORC_SUM) a = a + b;
+      else if (op == ORC_MAX) a = less_f64(a, b) ? b : a;
+      else if (op == ORC_MIN) a = less_f64(b, a) ? b : a;
+      *(double *)dst = a;
+      break;
+    }
+    case ORC_F32: {
+      float a = *(float *)dst, b = *(const float *)src;
+      if (op == ORC_SUM) a = a + b;
+      else if (op == ORC_MAX) a = less_f32(a, b) ? b : a;
+      else if (op == ORC_MIN) a = less_f32(b, a) ? b : a;
+      *(float *)dst = a;
+      break;
+    }
+    case ORC_I32: {
+      int32_t a = *(int32_t *)dst, b = *(const int32_t *)src;
+      if (op == ORC_SUM) a = (int32_t)((uint32_t)a + (uint32_t)b);
+      else if (op == ORC_MAX) a = a < b ? b : a;
+      else if (op == ORC_MIN) a = b < a ? b : a;
+      *(int32_t *)dst = a;
+      break;
+    }
+    case ORC_I64: {
+      int64_t a = *(int64_t *)dst, b = *(const int64_t *)src;
+      if (op == ORC_SUM) a = (int64_t)((uint64_t)a + (uint64_t)b);
+      else if (op == ORC_MAX) a = a < b ? b : a;
+      else if (op == ORC_MIN) a = b < a ? b : a;
+      *(int64_t *)dst = a;
+      break;
+    }
+    case ORC_PAIR: {
+      orc_pair *a = (orc_pair *)dst;
+      const orc_pair *b = (const orc_pair *)src;
+      if (op == ORC_MAXLOC && pair_better(b, a)) {
+        a->v = b->v;
+        a->i = b->i;
+      }
+      break;
+    }
+  }
+}
+
+static int op_valid(int dtype, int op) {
+  if (dtype == ORC_PAIR) return op == ORC_REPLACE || op == ORC_MAXLOC;
+  return op == ORC_REPLACE || op == ORC_SUM || op == ORC_MAX || op == ORC_MIN;
+}
+
+static int check_graph(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+                       int dtype, int bs) {
+  if (nroots < 0 || nleaves < 0 || bs < 1 || elem_size(dtype) < 0) return -1;
+  if (nleaves > 0 && !iroot) return -1;
+  for (int64_t i = 0; i < nleaves; i++) {
+    if (iroot[i] < 0 || iroot[i] >= nroots) return -1;
+    if (ilocal && ilocal[i] < 0) return -1;
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------- canonical pairwise */
+
+static int64_t largest_pow2_below(int64_t n) { /* n >= 2 */
+  int64_t m = 1;
+  while (m * 2 < n) m *= 2;
+  return m;
+}
+
+static double pw_f64_topdown(const double *x, int64_t n) {
+  if (n == 1) return x[0];
+  int64_t m = largest_pow2_below(n);
+  double a = pw_f64_topdown(x, m);
+  double b = pw_f64_topdown(x + m, n - m);
+  return a + b;
+}
+static float pw_f32_topdown(const float *x, int64_t n) {
+  if (n == 1) return x[0];
+  int64_t m = largest_pow2_below(n);
+  float a = pw_f32_topdown(x, m);
+  float b = pw_f32_topdown(x + m, n - m);
+  return a + b;
+}
+
+static double pw_f64_bottomup(const double *x, int64_t n) {
+  double *w = (double *)malloc((size_t)n * sizeof(double));
+  memcpy(w, x, (size_t)n * sizeof(double));
+  int64_t len = n;
+  while (len > 1) {
+    int64_t half = 0;
+    for (int64_t j = 0; j + 1 < len; j += 2) w[half++] = w[j] + w[j + 1];
+    if (len % 2) w[half++] = w[len - 1];
+    len = half;
+  }
+  double s = w[0];
+  free(w);
+  return s;
+}
+static float pw_f32_bottomup(const float *x, int64_t n) {
+  float *w = (float *)malloc((size_t)n * sizeof(float));
+  memcpy(w, x, (size_t)n * sizeof(float));
+  int64_t len = n;
+  while (len > 1) {
+    int64_t half = 0;
+    for (int64_t j = 0; j + 1 < len; j += 2) w[half++] = w[j] + w[j + 1];
+    if (len % 2) w[half++] = w[len - 1];
+    len = half;
+  }
+  float s = w[0];
+  free(w);
+  return s;
+}
+
+double orc_pairwise_f64(const double *x, int64_t n, int form) {
+  if (n < 1) return 0.0;
+  return form == ORC_PW_BOTTOMUP ? pw_f64_bottomup(x, n) : pw_f64_topdown(x, n);
+}
+float orc_pairwise_f32(const float *x, int64_t n, int form) {
+  if (n < 1) return 0.0f;
+  return form == ORC_PW_BOTTOMUP ? pw_f32_bottomup(x, n) : pw_f32_topdown(x, n);
+}
+
+/* ------------------------------------------------------------------ Bcast */
+
+int orc_bcast(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+              int dtype, int bs, int op, const void *rootdata, void *leafdata) {
+  if (check_graph(nroots, nleaves, ilocal, iroot, dtype, bs) || !op_valid(dtype, op)) return -1;
+  int64_t es = elem_size(dtype), us = es * bs;
+  const char *root = (const char *)rootdata;
+  char *leaf = (char *)leafdata;
+  for (int64_t i = 0; i < nleaves; i++) {
+    int64_t slot = ilocal ? ilocal[i] : i;
+    for (int c = 0; c < bs; c++)
+      apply_op(dtype, op, leaf + slot * us + c * es, root + iroot[i] * us + c * es);
+  }
+  return 0;
+}
+
+/* ----------------------------------------------------------------- Reduce */
+
+/* Leaf lists L_r in ascending leaf index, as a counting sort: start[r] is
+ * the first position of root r in order[], order[] holds leaf indices. */
+static void build_leaf_lists(int64_t nroots, int64_t nleaves, const int64_t *iroot,
+                             int64_t **start_out, int64_t **order_out) {
+  int64_t *start = (int64_t *)calloc((size_t)nroots + 1, sizeof(int64_t));
+  int64_t *fill = (int64_t *)calloc((size_t)nroots + 1, sizeof(int64_t));
+  int64_t *order = (int64_t *)malloc((size_t)(nleaves > 0 ? nleaves : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < nleaves; i++) start[iroot[i] + 1]++;
+  for (int64_t r = 0; r < nroots; r++) start[r + 1] += start[r];
+  for (int64_t r = 0; r < nroots; r++) fill[r] = start[r];
+  for (int64_t i = 0; i < nleaves; i++) order[fill[iroot[i]]++] = i;
+  free(fill);
+  *start_out = start;
+  *order_out = order;
+}
+
+int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+               int dtype, int bs, int op, const void *leafdata, void *rootdata, int pw_form) {
+  if (check_graph(nroots, nleaves, ilocal, iroot, dtype, bs) || !op_valid(dtype, op)) return -1;
+  int64_t es = elem_size(dtype), us = es * bs;
+  const char *leaf = (const char *)leafdata;
+  char *root = (char *)rootdata;
+  int64_t *start, *order;
+  build_leaf_lists(nroots, nleaves, iroot, &start, &order);
+  int64_t maxdeg = 0;
+  for (int64_t r = 0; r < nroots; r++)
+    if (start[r + 1] - start[r] > maxdeg) maxdeg = start[r + 1] - start[r];
+  void *tmp = malloc((size_t)(maxdeg > 0 ? maxdeg : 1) * 8);
+
+  for (int64_t r = 0; r < nroots; r++) {
+    int64_t deg = start[r + 1] - start[r];
+    if (deg == 0) continue;
+    const int64_t *Lr = order + start[r];
+    for (int c = 0; c < bs; c++) {
+      char *dst = root + r * us + c * es;
+      if (op == ORC_SUM && (dtype == ORC_F64 || dtype == ORC_F32)) {
+        /* root + PW(leaves in ascending leaf index) */
+        for (int64_t k = 0; k < deg; k++) {
+          int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
+          memcpy((char *)tmp + k * es, leaf + slot * us + c * es, (size_t)es);
+        }
+        if (dtype == ORC_F64) {
+          double t = orc_pairwise_f64((const double *)tmp, deg, pw_form);
+          *(double *)dst = *(double *)dst + t;
+        } else {
+          float t = orc_pairwise_f32((const float *)tmp, deg, pw_form);
+          *(float *)dst = *(float *)dst + t;
+        }
+      } else {
+        /* order-free ops (and REPLACE: the last leaf wins) folded in leaf order */
+        for (int64_t k = 0; k < deg; k++) {
+          int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
+          apply_op(dtype, op, dst, leaf + slot * us + c * es);
+        }
+      }
+    }
+  }
+  free(tmp);
+  free(start);
+  free(order);
+  return 0;
+}
+
+/* ------------------------------------------------------------ FetchAndOp */
+
+int orc_fetch_and_op(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+                     int dtype, int bs, int op, void *rootdata, const void *leafdata, void *leafupdate) {
+  if (check_graph(nroots, nleaves, ilocal, iroot, dtype, bs)) return -1;
+  if (dtype == ORC_PAIR || !(op == ORC_SUM || op == ORC_MAX || op == ORC_MIN)) return -1;
+  int64_t es = elem_size(dtype), us = es * bs;
+  char *root = (char *)rootdata;
+  const char *leaf = (const char *)leafdata;
+  char *upd = (char *)leafupdate;
+  for (int64_t i = 0; i < nleaves; i++) {
+    int64_t slot = ilocal ? ilocal[i] : i;
+    for (int c = 0; c < bs; c++) {
+      char *r = root + iroot[i] * us + c * es;
+      memcpy(upd + slot * us + c * es, r, (size_t)es);
+      apply_op(dtype, op, r, leaf + slot * us + c * es);
+    }
+  }
+  return 0;
+}

@@ -1,0 +1,76 @@
+/*
+ * sf_oracle.h -- plain CPU definitions of the star-forest (SF) communication
+ * operations, used ONLY as test infrastructure (pytest, the package smoke
+ * check and the CPU baseline leg of the benchmark).  The product path never
+ * links, loads or calls this code, and this code shares nothing with it: its
+ * own enums, its own header, its own loops.
+ *
+ * Notation follows the paper ("The PetscSF Scalable Communication Layer"):
+ *   leaf i in [0, nleaves) lives at slot l_i = ilocal[i] (or i when ilocal is
+ *   NULL) and is connected to root r_i = iroot[i] in [0, nroots)
+ *   (Section 3.1, PetscSFSetGraph).  L_r = { i : r_i = r } in ascending i.
+ *   Data are arrays of "units"; a unit is bs contiguous elements of one
+ *   type (Section 3.2: "unit is the data type of the tree vertices").
+ *
+ * Arithmetic is carried out in the unit's own type, since the unit (an MPI
+ * datatype in the paper) fixes the precision of MPI_SUM and friends.  Build
+ * with -O2 -fno-fast-math -ffp-contract=off so every floating-point operation
+ * happens exactly as written (no contraction to FMA, no reassociation).
+ *
+ * Every function returns 0 on success and -1 on an invalid argument.
+ */
+#ifndef SF_ORACLE_H
+#define SF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element types.  ORC_PAIR is the MAXLOC pair {double v; int32 i; int32 pad}
+ * with a 16-byte extent; pad is never read or written. */
+enum { ORC_F64 = 0, ORC_F32 = 1, ORC_I32 = 2, ORC_I64 = 3, ORC_PAIR = 4 };
+
+/* Operations (MPI_Op analogues, Section 3.2). */
+enum { ORC_REPLACE = 0, ORC_SUM = 1, ORC_MAX = 2, ORC_MIN = 3, ORC_MAXLOC = 4 };
+
+/* Forms of the canonical pairwise sum (see orc_pairwise_*). */
+enum { ORC_PW_TOPDOWN = 0, ORC_PW_BOTTOMUP = 1 };
+
+/* SFBcast (Section 3.2, item 1): for every leaf i,
+ *   leaf[l_i] = root[r_i]                 (op == REPLACE)
+ *   leaf[l_i] = op(leaf[l_i], root[r_i])  (SUM / MAX / MIN / MAXLOC)
+ * Slots that are not any l_i are left untouched (holes, Section 3.1). */
+int orc_bcast(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+              int dtype, int bs, int op, const void *rootdata, void *leafdata);
+
+/* SFReduce (Section 3.2, item 1, "vice versa"): for every root r with a
+ * non-empty L_r, combine the root's value with the values of its leaves:
+ *   FP SUM : root[r] = root[r] + PW(leaf[l_i] : i in L_r)  (pairwise, leaf order)
+ *   int SUM: two's-complement wrap-around
+ *   MAX/MIN: total order with -0 < +0 (NaN never occurs in the inputs)
+ *   MAXLOC : larger value wins, equal values -> smaller index wins
+ *   REPLACE: the last leaf of L_r wins
+ * Roots with an empty L_r are left untouched.  pw_form selects which of the
+ * two equivalent formulations of PW is used (they must agree bitwise). */
+int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+               int dtype, int bs, int op, const void *leafdata, void *rootdata, int pw_form);
+
+/* SFFetchAndOp (Section 3.2, item 2): for i = 0, 1, ..., nleaves-1 in turn,
+ *   leafupdate[l_i] = root[r_i];  root[r_i] = op(root[r_i], leaf[l_i]).
+ * op is SUM, MAX or MIN; dtype is not ORC_PAIR. */
+int orc_fetch_and_op(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
+                     int dtype, int bs, int op, void *rootdata, const void *leafdata, void *leafupdate);
+
+/* Canonical pairwise sum PW of x[0..n), n >= 1:
+ *   PW(x) = x[0] if n == 1, else PW(x[0..m)) + PW(x[m..n)),
+ *   m = the largest power of two strictly below n          (ORC_PW_TOPDOWN)
+ * or, equivalently, repeated levels that add neighbours (2j, 2j+1) with an
+ * unpaired last element passed up unchanged                 (ORC_PW_BOTTOMUP). */
+double orc_pairwise_f64(const double *x, int64_t n, int form);
+float orc_pairwise_f32(const float *x, int64_t n, int form);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
