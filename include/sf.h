@@ -1,0 +1,264 @@
+/*
+ * sf.h -- C ABI of the star-forest (SF) communication kernels for AMD
+ * MI355X (gfx950).
+ *
+ * The SF model is the one of "The PetscSF Scalable Communication Layer":
+ * a star is one root with zero or more leaves, a star forest is a union of
+ * disjoint stars, leaves without a root are holes (Section 3.1, Fig. 1).
+ * This library runs one device's share of an SF: every root is local, and
+ * the leaves that a would-be neighbour rank owns form one segment of a
+ * contiguous leaf buffer (Section 5.1 two-sided lists, Section 5.2 pack /
+ * unpack / scatter).  The data-parallel hot path -- the pack/unpack-with-
+ * reduction kernels behind SFBcast, SFReduce and SFFetchAndOp -- runs as
+ * hand-written HIP kernels on the caller's stream.
+ *
+ * Conventions for every call:
+ *  - Return value: SF_OK (0) on success, a negative sf_error otherwise; no
+ *    call aborts the process.  sf_error_string() describes a code.
+ *  - Host arguments (ilocal, iremote, opts, items, out-pointers) are read
+ *    during the call only, unless a copy mode says otherwise.
+ *  - Data arguments (rootdata, leafdata, leafupdate) are DEVICE pointers
+ *    owned by the caller, arrays of units (see sf_unit), aligned to the
+ *    unit's element size.  They are borrowed from *_begin to the matching
+ *    *_end and must not be modified in between (Section 3.2).
+ *  - stream is a hipStream_t (NULL = the null stream).  Begin enqueues the
+ *    kernels; End is stream-ordered and never blocks the host: results are
+ *    visible to later work on the same stream (or after synchronising it).
+ *  - Device indices are 32-bit: nroots and the leaf space must be < 2^31.
+ *  - An SF and its scratch memory may be used by one stream at a time.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- types */
+
+typedef struct sf_s *sf_t;             /* opaque SF handle (PetscSF, Section 3.1) */
+typedef struct sf_batch_s *sf_batch_t; /* opaque batch of SF operations */
+
+/* Root address of a leaf (PetscSFNode{rank, offset}, Section 3.1).  rank is
+ * the owner rank in the paper; on one device it is the segment label of the
+ * leaf (leaves of one label form one segment).  index is the local root. */
+typedef struct {
+  int64_t rank;
+  int64_t index;
+} sf_node;
+
+/* Ownership of ilocal / iremote (PetscCopyMode, Section 3.1). */
+typedef enum {
+  SF_COPY_VALUES = 0, /* the library copies the arrays */
+  SF_USE_POINTER = 1, /* the library borrows them until sf_destroy; caller keeps them unchanged */
+  SF_OWN_POINTER = 2  /* not supported: returns SF_ERR_UNSUPPORTED */
+} sf_copymode;
+
+/* Element type of a unit.  SF_F64_I32 is the MAXLOC pair
+ * struct { double v; int32_t i; int32_t pad; } with a 16-byte extent; pad is
+ * never read or written. */
+typedef enum { SF_F64 = 0, SF_F32 = 1, SF_I32 = 2, SF_I64 = 3, SF_F64_I32 = 4 } sf_dtype;
+
+/* A unit is bs contiguous elements of one dtype: the "unit" MPI datatype of
+ * Section 3.2.  Ops act per element (MAXLOC: per pair). */
+typedef struct {
+  int32_t dtype; /* sf_dtype */
+  int32_t bs;    /* block size, >= 1 */
+} sf_unit;
+
+/* Operation (MPI_Op of Section 3.2). */
+typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4 } sf_op;
+
+/* How SFReduce combines leaves of a root that has several (Section 5.3 uses
+ * atomics when destinations repeat).
+ *  AUTO          : atomic for order-free ops and FP SUM, deterministic for
+ *                  MAXLOC and REPLACE;
+ *  ATOMIC        : native atomics, with block-local aggregation of the
+ *                  roots of highest degree; FP SUM order is unspecified;
+ *  DETERMINISTIC : root-sorted segmented reduction; FP SUM is the
+ *                  canonical pairwise sum of the root's leaves in ascending
+ *                  leaf index, added to the root (root on the left);
+ *                  bit-identical for every launch configuration.
+ * Roots with a single leaf never need atomics. */
+typedef enum { SF_REDUCE_AUTO = 0, SF_REDUCE_ATOMIC = 1, SF_REDUCE_DETERMINISTIC = 2 } sf_reduce_mode;
+
+/* Options of sf_setup (NULL = all defaults). */
+typedef struct {
+  int32_t reduce_mode;  /* sf_reduce_mode, default AUTO */
+  int32_t use_patterns; /* 1 (default): detect contiguous / 3-D sub-block index patterns */
+  int32_t analyze_only; /* 1: host analysis only, no device memory (for inspection) */
+  int32_t reserved;
+} sf_setup_opts;
+
+/* Index pattern of one side of one segment (Section 5.2): index(t) for the
+ * t-th leaf of the segment, t = i + dx*(j + dy*k), 0 <= i < dx, 0 <= j < dy,
+ * 0 <= k < dz, is start + i + sy*j + sz*k (sy = X, sz = X*Y of the paper). */
+typedef enum { SF_PATTERN_GENERIC = 0, SF_PATTERN_CONTIGUOUS = 1, SF_PATTERN_3D = 2 } sf_pattern_kind;
+typedef struct {
+  int32_t kind; /* sf_pattern_kind */
+  int32_t start, dx, dy, dz, sy, sz;
+} sf_pattern;
+
+typedef struct {
+  int64_t rank;    /* segment label */
+  int64_t nleaves; /* leaves in the segment */
+  sf_pattern root; /* pattern of the roots r_i of the segment's leaves */
+  sf_pattern leaf; /* pattern of the leaf slots l_i */
+} sf_segment_info;
+
+typedef struct {
+  int64_t nroots, nleaves;
+  int64_t leafspace;      /* slots a leaf buffer must hold: max(ilocal)+1, or nleaves */
+  int64_t nsegments;
+  int64_t nroots_touched; /* roots of degree >= 1 */
+  int64_t max_degree;
+  int32_t has_dup_roots;  /* some root has degree >= 2 */
+  int32_t reduce_mode;    /* current sf_reduce_mode */
+  int64_t nhot;           /* roots aggregated in LDS by the atomic path */
+  int64_t device_bytes;   /* device memory held by the plan */
+} sf_info;
+
+/* Error codes. */
+typedef enum {
+  SF_OK = 0,
+  SF_ERR_ARG = -1,         /* bad argument: size, index out of range, null pointer, misalignment */
+  SF_ERR_DUP_LEAF = -2,    /* two leaves share a slot: stars must be disjoint (Section 3.1) */
+  SF_ERR_NOT_SETUP = -3,   /* operation before sf_setup */
+  SF_ERR_UNSUPPORTED = -4, /* unit/op combination or mode not provided */
+  SF_ERR_HIP = -5,         /* HIP runtime or launch error */
+  SF_ERR_OOM = -6,         /* device or host allocation failed */
+  SF_ERR_MISMATCH = -7,    /* *_end without a matching *_begin with the same arguments */
+  SF_ERR_BUSY = -8         /* *_begin while the same operation on the same buffers is pending */
+} sf_error;
+
+/* ------------------------------------------------------------- creation */
+
+/* PetscSFCreate + PetscSFSetGraph (Section 3.1).
+ *  nroots   : roots owned here, numbered 0..nroots-1.
+ *  nleaves  : connected leaves.
+ *  ilocal   : [nleaves] leaf slots (distinct, >= 0), or NULL for slots
+ *             0..nleaves-1 (contiguous leaf space).
+ *  iremote  : [nleaves] root address of each leaf; index in [0, nroots).
+ *  localmode, remotemode: sf_copymode of the two arrays.
+ *  out      : receives the new handle (NULL on error).
+ * Errors: SF_ERR_ARG (negative sizes, index out of range, sizes >= 2^31,
+ * NULL iremote with nleaves > 0), SF_ERR_DUP_LEAF, SF_ERR_UNSUPPORTED
+ * (SF_OWN_POINTER), SF_ERR_OOM. */
+int sf_create(int64_t nroots, int64_t nleaves, const int64_t *ilocal, int32_t localmode,
+              const sf_node *iremote, int32_t remotemode, sf_t *out);
+
+/* PetscSFSetUp (Section 3.1: internal structures, all optimisations, cost
+ * amortised over many operations).  Groups leaves into segments by rank
+ * (stable), detects per-segment index patterns (Section 5.2), detects
+ * duplicate roots (Section 5.3), builds the root-sorted leaf lists of the
+ * deterministic reduction and the hot-root table of the atomic one, and
+ * uploads the index plan to the current device.  Synchronous.  Calling it
+ * again rebuilds the plan with the new options. */
+int sf_setup(sf_t sf, const sf_setup_opts *opts);
+
+/* Change the reduce mode of a set-up SF (sf_reduce_mode). */
+int sf_set_reduce_mode(sf_t sf, int32_t mode);
+
+/* --------------------------------------------------------- communication */
+
+/* SFBcast (Section 3.2, item 1): root -> leaves.  For every leaf i,
+ * leafdata[l_i] = rootdata[r_i] (REPLACE) or op(leafdata[l_i], rootdata[r_i])
+ * (SUM, MAX, MIN; MAXLOC on F64_I32).  Holes are not touched.
+ *  rootdata: [nroots] units; leafdata: [leafspace] units. */
+int sf_bcast_begin(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, int32_t op,
+                   hipStream_t stream);
+int sf_bcast_end(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, int32_t op,
+                 hipStream_t stream);
+
+/* SFReduce (Section 3.2, item 1, "vice versa"): leaves -> root, the root's
+ * own value taking part (Section 4.1 adds B^T x back onto y).  Roots without
+ * leaves are not touched.  REPLACE: the last leaf in leaf order wins
+ * (deterministic mode; in atomic mode some leaf wins).  MAXLOC: larger
+ * value wins, equal values go to the smaller index.  MAX/MIN order -0 < +0.
+ *  leafdata: [leafspace] units; rootdata: [nroots] units. */
+int sf_reduce_begin(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
+                    hipStream_t stream);
+int sf_reduce_end(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
+                  hipStream_t stream);
+
+/* SFFetchAndOp (Section 3.2, item 2), op = SUM: every leaf i fetches the
+ * current partial value of its root into leafupdate[l_i], then adds
+ * leafdata[l_i] to it.  Deterministic mode (integer units): leaves are
+ * applied in ascending leaf index, the result equals the sequential
+ * definition bit for bit.  Atomic mode (any non-pair unit): each root's
+ * leaves are applied in some order; the final root is the same, the fetched
+ * values are the partial sums of that order.
+ *  rootdata: [nroots] units, updated in place; leafdata, leafupdate:
+ *  [leafspace] units (must not overlap). */
+int sf_fetch_and_op_begin(sf_t sf, sf_unit unit, void *rootdata, const void *leafdata,
+                          void *leafupdate, int32_t op, hipStream_t stream);
+int sf_fetch_and_op_end(sf_t sf, sf_unit unit, void *rootdata, const void *leafdata,
+                        void *leafupdate, int32_t op, hipStream_t stream);
+
+/* --------------------------------------------------------------- batches */
+
+typedef enum { SF_KIND_BCAST = 0, SF_KIND_REDUCE = 1 } sf_kind;
+
+/* One operation of a batch: an SF (set up), a unit, a kind, an op and the
+ * device buffers (roots, leaves). */
+typedef struct {
+  sf_t sf;
+  sf_unit unit;
+  int32_t kind; /* sf_kind */
+  int32_t op;   /* REPLACE for Bcast; SUM for Reduce */
+  void *rootdata;
+  void *leafdata;
+} sf_batch_item;
+
+/* Batch many independent SF operations (uneven sizes, units and kinds) so
+ * that they run in ONE persistent kernel launch (Section 5.4: launch costs
+ * that small kernels cannot hide).  The work table is built once here; the
+ * buffers of the items are bound to the batch (the same pointers are used by
+ * every launch).  The items' SFs must stay alive while the batch exists and
+ * no two items may write the same buffer.  Reduce items use atomics for
+ * roots of several leaves unless their SF is in DETERMINISTIC mode. */
+int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t *out);
+
+/* Run every item of the batch in one launch on stream. */
+int sf_batch_launch(sf_batch_t batch, hipStream_t stream);
+
+/* Run the items one kernel launch per item (the per-SF comparison). */
+int sf_batch_launch_separate(sf_batch_t batch, hipStream_t stream);
+
+/* Capture the batch's launch sequence (mode 0: the single persistent
+ * launch, mode 1: one launch per item) into a HIP graph on stream; later
+ * sf_batch_graph_launch calls replay it. */
+int sf_batch_graph_capture(sf_batch_t batch, int32_t mode, hipStream_t stream);
+int sf_batch_graph_launch(sf_batch_t batch, hipStream_t stream);
+
+/* Time the candidate launch shapes (leaves per thread x tile size) of the
+ * persistent kernel on stream and keep the fastest.  cache_path (may be
+ * NULL) names a text file of earlier choices keyed by the batch's shape: a
+ * hit skips the timing, a miss appends the result.  The candidates are
+ * bit-identical in every result that is deterministic.  Launches the batch
+ * several times: the item buffers are overwritten. */
+int sf_batch_autotune(sf_batch_t batch, const char *cache_path, hipStream_t stream);
+
+/* Current launch shape (leaves per thread, tile leaves) and work tiles. */
+int sf_batch_get_config(sf_batch_t batch, int32_t *lpt, int32_t *tile, int64_t *ntiles);
+int sf_batch_set_config(sf_batch_t batch, int32_t lpt, int32_t tile);
+int sf_batch_destroy(sf_batch_t *batch);
+
+/* ----------------------------------------------------------- inspection */
+
+int sf_get_info(sf_t sf, sf_info *info);
+/* Segment s (0 <= s < nsegments) after sf_setup. */
+int sf_get_segment(sf_t sf, int64_t s, sf_segment_info *seg);
+const char *sf_error_string(int code);
+/* The HIP error behind the last SF_ERR_HIP of the calling thread. */
+int sf_last_hip_error(void);
+/* Destroy the SF, free its device memory; *sf is set to NULL. */
+int sf_destroy(sf_t *sf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SF_H */

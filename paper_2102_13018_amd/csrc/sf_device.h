@@ -1,0 +1,362 @@
+// sf_device.h -- device-side element types, operations and index helpers
+// shared by the star-forest kernels (single and batched).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sf_internal.h"
+
+namespace sfi {
+
+// MAXLOC unit {double v; int32 i; int32 pad}: only v and i are touched.
+struct Pair {
+  double v;
+  int32_t i;
+  int32_t pad;
+};
+
+// Total-order key of a float / double: unsigned compare of the key orders
+// the values with -0 < +0 (no NaN in the inputs).
+__device__ __forceinline__ uint64_t fkey(double x) {
+  const int64_t b = __double_as_longlong(x);
+  return b < 0 ? ~(uint64_t)b : ((uint64_t)b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ uint32_t fkey(float x) {
+  const int32_t b = __float_as_int(x);
+  return b < 0 ? ~(uint32_t)b : ((uint32_t)b | 0x80000000u);
+}
+
+enum OpCode { OP_REPLACE = SF_REPLACE, OP_SUM = SF_SUM, OP_MAX = SF_MAX, OP_MIN = SF_MIN, OP_MAXLOC = SF_MAXLOC };
+
+// a (left operand) op b
+template <int OP, typename T>
+struct Op;
+
+template <int OP>
+struct Op<OP, double> {
+  static __device__ __forceinline__ double apply(double a, double b) {
+    if (OP == OP_SUM) return a + b;
+    if (OP == OP_MAX) return fkey(a) < fkey(b) ? b : a;
+    if (OP == OP_MIN) return fkey(b) < fkey(a) ? b : a;
+    return b;
+  }
+};
+template <int OP>
+struct Op<OP, float> {
+  static __device__ __forceinline__ float apply(float a, float b) {
+    if (OP == OP_SUM) return a + b;
+    if (OP == OP_MAX) return fkey(a) < fkey(b) ? b : a;
+    if (OP == OP_MIN) return fkey(b) < fkey(a) ? b : a;
+    return b;
+  }
+};
+template <int OP>
+struct Op<OP, int32_t> {
+  static __device__ __forceinline__ int32_t apply(int32_t a, int32_t b) {
+    if (OP == OP_SUM) return (int32_t)((uint32_t)a + (uint32_t)b);
+    if (OP == OP_MAX) return a < b ? b : a;
+    if (OP == OP_MIN) return b < a ? b : a;
+    return b;
+  }
+};
+template <int OP>
+struct Op<OP, int64_t> {
+  static __device__ __forceinline__ int64_t apply(int64_t a, int64_t b) {
+    if (OP == OP_SUM) return (int64_t)((uint64_t)a + (uint64_t)b);
+    if (OP == OP_MAX) return a < b ? b : a;
+    if (OP == OP_MIN) return b < a ? b : a;
+    return b;
+  }
+};
+template <int OP>
+struct Op<OP, Pair> {
+  static __device__ __forceinline__ Pair apply(Pair a, Pair b) {
+    if (OP == OP_MAXLOC) {
+      const uint64_t ka = fkey(a.v), kb = fkey(b.v);
+      const bool better = kb > ka || (kb == ka && b.i < a.i);
+      return better ? b : a;
+    }
+    return b;
+  }
+};
+
+// Element loads / stores.  Pair stores never write the padding word.
+template <typename T>
+__device__ __forceinline__ T ld(const T *p) {
+  return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st(T *p, T v) {
+  *p = v;
+}
+template <>
+__device__ __forceinline__ Pair ld<Pair>(const Pair *p) {
+  Pair r;
+  r.v = p->v;
+  r.i = p->i;
+  r.pad = 0;
+  return r;
+}
+template <>
+__device__ __forceinline__ void st<Pair>(Pair *p, Pair v) {
+  p->v = v.v;
+  p->i = v.i;
+}
+
+// Cross-lane move of an element (ds_bpermute based shuffles).
+__device__ __forceinline__ double shfl_down(double v, int d) { return __shfl_down(v, d); }
+__device__ __forceinline__ float shfl_down(float v, int d) { return __shfl_down(v, d); }
+__device__ __forceinline__ int32_t shfl_down(int32_t v, int d) { return __shfl_down(v, d); }
+__device__ __forceinline__ int64_t shfl_down(int64_t v, int d) {
+  return (int64_t)__shfl_down((long long)v, d);
+}
+__device__ __forceinline__ Pair shfl_down(Pair v, int d) {
+  Pair r;
+  r.v = __shfl_down(v.v, d);
+  r.i = __shfl_down(v.i, d);
+  r.pad = 0;
+  return r;
+}
+__device__ __forceinline__ int32_t shfl_up(int32_t v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ int64_t shfl_up(int64_t v, int d) { return (int64_t)__shfl_up((long long)v, d); }
+__device__ __forceinline__ double shfl_up(double v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d); }
+
+// Index of the t-th leaf of a segment side with a pattern (Section 5.2).
+__device__ __forceinline__ int32_t pat_index(const DevPattern &p, int32_t t) {
+  if (p.kind == SF_PATTERN_CONTIGUOUS) return p.start + t;
+  const uint32_t ut = (uint32_t)t;
+  const uint32_t i = ut % (uint32_t)p.dx;
+  const uint32_t q = ut / (uint32_t)p.dx;
+  const uint32_t j = q % (uint32_t)p.dy;
+  const uint32_t k = q / (uint32_t)p.dy;
+  return p.start + (int32_t)i + p.sy * (int32_t)j + p.sz * (int32_t)k;
+}
+
+__device__ __forceinline__ int32_t seg_root(const DevSegment &s, const int32_t *__restrict__ ridx, int32_t t) {
+  return s.root.kind == SF_PATTERN_GENERIC ? ridx[s.roff + t] : pat_index(s.root, t);
+}
+__device__ __forceinline__ int32_t seg_leaf(const DevSegment &s, const int32_t *__restrict__ lidx, int32_t t) {
+  return s.leaf.kind == SF_PATTERN_GENERIC ? lidx[s.loff + t] : pat_index(s.leaf, t);
+}
+
+// ------------------------------------------------------------- atomics
+// root (global memory) op= v, atomically, device scope.
+template <int OP, typename T>
+struct AtomicG;
+
+template <int OP>
+struct AtomicG<OP, double> {
+  static __device__ __forceinline__ void run(double *p, double v) {
+    if (OP == OP_SUM) {
+      unsafeAtomicAdd(p, v);
+    } else {
+      // MAX/MIN under the total order through integer atomics on the bits:
+      // for a non-negative v the signed order of the bit patterns is the
+      // value order, for a negative v the unsigned order is reversed.
+      // MIN mirrors it: signed min for v >= 0, unsigned max for v < 0.
+      const int64_t b = __double_as_longlong(v);
+      if (OP == OP_MAX) {
+        if (b >= 0)
+          __hip_atomic_fetch_max(reinterpret_cast<long long *>(p), (long long)b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(p), (unsigned long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (b >= 0)
+          __hip_atomic_fetch_min(reinterpret_cast<long long *>(p), (long long)b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          __hip_atomic_fetch_max(reinterpret_cast<unsigned long long *>(p), (unsigned long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+};
+template <int OP>
+struct AtomicG<OP, float> {
+  static __device__ __forceinline__ void run(float *p, float v) {
+    if (OP == OP_SUM) {
+      unsafeAtomicAdd(p, v);
+    } else {
+      const int32_t b = __float_as_int(v);
+      if (OP == OP_MAX) {
+        if (b >= 0)
+          __hip_atomic_fetch_max(reinterpret_cast<int *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          __hip_atomic_fetch_min(reinterpret_cast<unsigned int *>(p), (unsigned int)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (b >= 0)
+          __hip_atomic_fetch_min(reinterpret_cast<int *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          __hip_atomic_fetch_max(reinterpret_cast<unsigned int *>(p), (unsigned int)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+};
+template <int OP>
+struct AtomicG<OP, int32_t> {
+  static __device__ __forceinline__ void run(int32_t *p, int32_t v) {
+    if (OP == OP_SUM)
+      __hip_atomic_fetch_add(reinterpret_cast<unsigned int *>(p), (unsigned int)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (OP == OP_MAX)
+      __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+template <int OP>
+struct AtomicG<OP, int64_t> {
+  static __device__ __forceinline__ void run(int64_t *p, int64_t v) {
+    if (OP == OP_SUM)
+      __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    else if (OP == OP_MAX)
+      __hip_atomic_fetch_max(reinterpret_cast<long long *>(p), (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_fetch_min(reinterpret_cast<long long *>(p), (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// Same operations on LDS (workgroup scope).
+template <int OP, typename T>
+struct AtomicL;
+
+template <int OP>
+struct AtomicL<OP, double> {
+  static __device__ __forceinline__ void run(double *p, double v) {
+    if (OP == OP_SUM) {
+      __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      const int64_t b = __double_as_longlong(v);
+      if (OP == OP_MAX) {
+        if (b >= 0)
+          __hip_atomic_fetch_max(reinterpret_cast<long long *>(p), (long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(p), (unsigned long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        if (b >= 0)
+          __hip_atomic_fetch_min(reinterpret_cast<long long *>(p), (long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_max(reinterpret_cast<unsigned long long *>(p), (unsigned long long)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+};
+template <int OP>
+struct AtomicL<OP, float> {
+  static __device__ __forceinline__ void run(float *p, float v) {
+    if (OP == OP_SUM) {
+      __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      const int32_t b = __float_as_int(v);
+      if (OP == OP_MAX) {
+        if (b >= 0)
+          __hip_atomic_fetch_max(reinterpret_cast<int *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_min(reinterpret_cast<unsigned int *>(p), (unsigned int)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        if (b >= 0)
+          __hip_atomic_fetch_min(reinterpret_cast<int *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_max(reinterpret_cast<unsigned int *>(p), (unsigned int)b, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+};
+template <int OP>
+struct AtomicL<OP, int32_t> {
+  static __device__ __forceinline__ void run(int32_t *p, int32_t v) {
+    if (OP == OP_SUM)
+      __hip_atomic_fetch_add(reinterpret_cast<unsigned int *>(p), (unsigned int)v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    else if (OP == OP_MAX)
+      __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+template <int OP>
+struct AtomicL<OP, int64_t> {
+  static __device__ __forceinline__ void run(int64_t *p, int64_t v) {
+    if (OP == OP_SUM)
+      __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    else if (OP == OP_MAX)
+      __hip_atomic_fetch_max(reinterpret_cast<long long *>(p), (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_fetch_min(reinterpret_cast<long long *>(p), (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// Identity of an op on type T (start value of the LDS accumulators).
+template <int OP, typename T>
+__device__ __forceinline__ T op_identity() {
+  if (OP == OP_SUM) return T(0);
+  return T(0);
+}
+template <>
+__device__ __forceinline__ double op_identity<OP_MAX, double>() {
+  return -__builtin_huge_val();
+}
+template <>
+__device__ __forceinline__ double op_identity<OP_MIN, double>() {
+  return __builtin_huge_val();
+}
+template <>
+__device__ __forceinline__ float op_identity<OP_MAX, float>() {
+  return -__builtin_huge_valf();
+}
+template <>
+__device__ __forceinline__ float op_identity<OP_MIN, float>() {
+  return __builtin_huge_valf();
+}
+template <>
+__device__ __forceinline__ int32_t op_identity<OP_MAX, int32_t>() {
+  return INT32_MIN;
+}
+template <>
+__device__ __forceinline__ int32_t op_identity<OP_MIN, int32_t>() {
+  return INT32_MAX;
+}
+template <>
+__device__ __forceinline__ int64_t op_identity<OP_MAX, int64_t>() {
+  return INT64_MIN;
+}
+template <>
+__device__ __forceinline__ int64_t op_identity<OP_MIN, int64_t>() {
+  return INT64_MAX;
+}
+
+// Fetch-and-add returning the previous value (device scope).
+__device__ __forceinline__ int32_t fetch_add_g(int32_t *p, int32_t v) {
+  return (int32_t)__hip_atomic_fetch_add(reinterpret_cast<unsigned int *>(p), (unsigned int)v, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t fetch_add_g(int64_t *p, int64_t v) {
+  return (int64_t)__hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double fetch_add_g(double *p, double v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float fetch_add_g(float *p, float v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace sfi
+
+namespace sfi {
+// a - b with two's-complement wrap-around.
+__device__ __forceinline__ int32_t wrap_sub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
+__device__ __forceinline__ int64_t wrap_sub(int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }
+}  // namespace sfi

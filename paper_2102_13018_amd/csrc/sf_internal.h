@@ -1,0 +1,150 @@
+// sf_internal.h -- plan structures shared by the host runtime and the
+// device kernels of the star-forest library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sf.h"
+
+namespace sfi {
+
+// ------------------------------------------------------------------ limits
+constexpr int kBlock = 256;          // threads per block of the stream kernels
+constexpr int kTileLeaves = 2048;    // leaves per work tile of the stream kernels
+constexpr int kChunkLPT = 4;         // leaves per lane of the wave-chunk reduction
+constexpr int kChunk = 64 * kChunkLPT;  // leaves per aligned chunk (power of two)
+constexpr int kSmallMaxDeg = 32;     // largest degree of the per-thread classes
+constexpr int kNumClasses = 6;       // degree classes 1, 2, 4, 8, 16, 32
+constexpr int kHotMax = 2048;        // roots aggregated in LDS by the atomic path
+constexpr int kHotLdsBytes = 32768;  // LDS budget for those accumulators
+constexpr int kPersistBlocks = 2048; // grid of the persistent atomic kernels
+
+// --------------------------------------------------------- device structs
+// Pattern of one side of a segment: index(t) = start + i + sy*j + sz*k with
+// t = i + dx*(j + dy*k).  kind: SF_PATTERN_GENERIC / CONTIGUOUS / 3D.
+struct DevPattern {
+  int32_t kind, start, dx, dy, sy, sz;
+};
+
+struct DevSegment {
+  int32_t n;        // leaves in the segment
+  int32_t roff;     // offset of the segment in the root-index array (generic root side)
+  int32_t loff;     // offset of the segment in the leaf-slot array (generic leaf side)
+  int32_t pad;
+  DevPattern root;
+  DevPattern leaf;
+};
+
+struct DevTile {  // leaves [t0, t1) of segment seg
+  int32_t seg, t0, t1, pad;
+};
+
+struct DevChunk {  // one aligned chunk of a root's (sorted) value list
+  int32_t src;  // first element in the level's input sequence
+  int32_t n;    // elements, 1..kChunk
+  int32_t dst;  // >= 0: slot in the next level's sequence; < 0: final, root = -dst-1
+  int32_t pad;
+};
+
+// ------------------------------------------------------------- host plan
+struct Segment {
+  int64_t rank;
+  std::vector<int64_t> members;  // leaf indices, ascending
+  sf_pattern root{}, leaf{};
+};
+
+struct ChunkLevel {
+  std::vector<DevChunk> chunks;
+  int64_t out_len = 0;  // length of the sequence this level writes
+};
+
+struct HostPlan {
+  // segments and tiles of the stream kernels
+  std::vector<DevSegment> dsegs;
+  std::vector<DevTile> tiles;
+  std::vector<int32_t> ridx;      // root index per processed leaf (generic root sides)
+  std::vector<int32_t> ridx_hot;  // same, hot roots encoded as -(h+1)
+  std::vector<int32_t> lidx;      // leaf slot per processed leaf (generic leaf sides)
+  std::vector<int32_t> hot_roots; // root id of hot slot h
+  // root-sorted lists
+  std::vector<int32_t> troot;     // touched roots, ascending
+  std::vector<int32_t> toff;      // [ntouched+1] offsets into sl
+  std::vector<int32_t> sl;        // leaf slot of the g-th leaf in (root, leaf) order
+  std::vector<int32_t> cls[kNumClasses];  // touched-root ordinals per degree class
+  std::vector<int32_t> large;     // touched-root ordinals with degree > kSmallMaxDeg
+  std::vector<ChunkLevel> levels; // chunk levels of the large roots
+  int64_t scratch_len = 0;        // max sequence length written by a chunk level
+  // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
+  std::vector<DevChunk> fo_chunks;
+  std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
+};
+
+// Device copy of the plan: one allocation, typed views into it.
+struct DevPlan {
+  void *blob = nullptr;
+  size_t bytes = 0;
+  DevSegment *segs = nullptr;
+  DevTile *tiles = nullptr;
+  int32_t *ridx = nullptr, *ridx_hot = nullptr, *lidx = nullptr, *hot_roots = nullptr;
+  int32_t *troot = nullptr, *toff = nullptr, *sl = nullptr;
+  int32_t *cls[kNumClasses] = {};
+  int32_t *large = nullptr;
+  std::vector<DevChunk *> levels;
+  DevChunk *fo_chunks = nullptr;
+  int32_t *fo_root_first = nullptr;
+};
+
+struct Pending {
+  int kind;  // 0 bcast, 1 reduce, 2 fetch-and-op
+  int32_t dtype, bs, op;
+  const void *a, *b, *c;
+};
+
+}  // namespace sfi
+
+struct sf_s {
+  int64_t nroots = 0, nleaves = 0, leafspace = 0;
+  const int64_t *ilocal = nullptr;  // borrowed or owned copy (may be null)
+  const sf_node *iremote = nullptr;
+  std::vector<int64_t> ilocal_copy;
+  std::vector<sf_node> iremote_copy;
+  bool setup = false;
+  bool analyzed = false;
+  sf_setup_opts opts{};
+  int32_t reduce_mode = SF_REDUCE_AUTO;
+  // analysis results
+  std::vector<sfi::Segment> segments;
+  sfi::HostPlan hp;
+  int64_t max_degree = 0;
+  bool has_dup_roots = false;
+  int device = -1;
+  sfi::DevPlan dp;
+  // scratch for chunk levels / MAXLOC passes, grown on demand
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::vector<sfi::Pending> pending;
+  std::mutex mu;
+};
+
+namespace sfi {
+// helpers implemented in sf_plan.cpp
+int analyze(sf_s *sf);
+sf_pattern detect_pattern(const int64_t *idx, int64_t n);
+int upload(sf_s *sf);
+void free_device(sf_s *sf);
+int set_hip_error(hipError_t e);
+int ensure_scratch(sf_s *sf, size_t bytes);
+
+// kernel launchers implemented in sf_kernels.hip
+int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, hipStream_t st);
+int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, hipStream_t st);
+int launch_fetch_and_op(sf_s *sf, sf_unit unit, void *root, const void *leaf, void *upd, int op,
+                        hipStream_t st);
+int elem_size(int32_t dtype);
+}  // namespace sfi

@@ -1,0 +1,311 @@
+"""Thin ctypes binding of libsf.so (include/sf.h): the same calls, with
+argument marshalling only.  Every step of an SF operation runs in the HIP
+kernels of the library; PyTorch only provides device memory and streams.
+
+If libsf.so is missing, :func:`lib` raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libsf.so")
+
+# enums of sf.h
+SF_F64, SF_F32, SF_I32, SF_I64, SF_F64_I32 = 0, 1, 2, 3, 4
+SF_REPLACE, SF_SUM, SF_MAX, SF_MIN, SF_MAXLOC = 0, 1, 2, 3, 4
+SF_REDUCE_AUTO, SF_REDUCE_ATOMIC, SF_REDUCE_DETERMINISTIC = 0, 1, 2
+SF_COPY_VALUES, SF_USE_POINTER, SF_OWN_POINTER = 0, 1, 2
+SF_KIND_BCAST, SF_KIND_REDUCE = 0, 1
+SF_PATTERN_GENERIC, SF_PATTERN_CONTIGUOUS, SF_PATTERN_3D = 0, 1, 2
+ERRORS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_DUP_LEAF", -3: "SF_ERR_NOT_SETUP",
+          -4: "SF_ERR_UNSUPPORTED", -5: "SF_ERR_HIP", -6: "SF_ERR_OOM", -7: "SF_ERR_MISMATCH",
+          -8: "SF_ERR_BUSY"}
+OPS = {"replace": SF_REPLACE, "sum": SF_SUM, "max": SF_MAX, "min": SF_MIN, "maxloc": SF_MAXLOC}
+MODES = {"auto": SF_REDUCE_AUTO, "atomic": SF_REDUCE_ATOMIC, "deterministic": SF_REDUCE_DETERMINISTIC}
+ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16}
+
+EXPORTS = [
+    "sf_create", "sf_setup", "sf_set_reduce_mode", "sf_bcast_begin", "sf_bcast_end",
+    "sf_reduce_begin", "sf_reduce_end", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
+    "sf_batch_create", "sf_batch_launch", "sf_batch_launch_separate", "sf_batch_graph_capture",
+    "sf_batch_graph_launch", "sf_batch_autotune", "sf_batch_get_config", "sf_batch_set_config",
+    "sf_batch_destroy", "sf_get_info", "sf_get_segment", "sf_error_string", "sf_last_hip_error",
+    "sf_destroy",
+]
+
+
+class SfError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = ERRORS.get(code, str(code))
+        if code == -5:
+            msg += f" (hipError {lib().sf_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+
+
+class SfNode(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("index", ctypes.c_int64)]
+
+
+class SfUnit(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("bs", ctypes.c_int32)]
+
+
+class SfSetupOpts(ctypes.Structure):
+    _fields_ = [("reduce_mode", ctypes.c_int32), ("use_patterns", ctypes.c_int32),
+                ("analyze_only", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SfPattern(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("start", ctypes.c_int32), ("dx", ctypes.c_int32),
+                ("dy", ctypes.c_int32), ("dz", ctypes.c_int32), ("sy", ctypes.c_int32),
+                ("sz", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SfSegmentInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("nleaves", ctypes.c_int64), ("root", SfPattern),
+                ("leaf", SfPattern)]
+
+
+class SfInfo(ctypes.Structure):
+    _fields_ = [("nroots", ctypes.c_int64), ("nleaves", ctypes.c_int64), ("leafspace", ctypes.c_int64),
+                ("nsegments", ctypes.c_int64), ("nroots_touched", ctypes.c_int64),
+                ("max_degree", ctypes.c_int64), ("has_dup_roots", ctypes.c_int32),
+                ("reduce_mode", ctypes.c_int32), ("nhot", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class SfBatchItem(ctypes.Structure):
+    _fields_ = [("sf", ctypes.c_void_p), ("unit", SfUnit), ("kind", ctypes.c_int32),
+                ("op", ctypes.c_int32), ("rootdata", ctypes.c_void_p), ("leafdata", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsf.so (built in-tree); raise if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is missing: build it with `python -m paper_2102_13018_amd.build`")
+        L = ctypes.CDLL(_SO)
+        p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sf_create.argtypes = [i64, i64, p, i32, p, i32, ctypes.POINTER(p)]
+        L.sf_setup.argtypes = [p, ctypes.POINTER(SfSetupOpts)]
+        L.sf_set_reduce_mode.argtypes = [p, i32]
+        for name in ("sf_bcast_begin", "sf_bcast_end", "sf_reduce_begin", "sf_reduce_end"):
+            getattr(L, name).argtypes = [p, SfUnit, p, p, i32, p]
+        for name in ("sf_fetch_and_op_begin", "sf_fetch_and_op_end"):
+            getattr(L, name).argtypes = [p, SfUnit, p, p, p, i32, p]
+        L.sf_batch_create.argtypes = [i32, ctypes.POINTER(SfBatchItem), ctypes.POINTER(p)]
+        L.sf_batch_launch.argtypes = [p, p]
+        L.sf_batch_launch_separate.argtypes = [p, p]
+        L.sf_batch_graph_capture.argtypes = [p, i32, p]
+        L.sf_batch_graph_launch.argtypes = [p, p]
+        L.sf_batch_autotune.argtypes = [p, ctypes.c_char_p, p]
+        L.sf_batch_get_config.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.sf_batch_set_config.argtypes = [p, i32, i32]
+        L.sf_batch_destroy.argtypes = [ctypes.POINTER(p)]
+        L.sf_get_info.argtypes = [p, ctypes.POINTER(SfInfo)]
+        L.sf_get_segment.argtypes = [p, i64, ctypes.POINTER(SfSegmentInfo)]
+        L.sf_error_string.argtypes = [ctypes.c_int]
+        L.sf_error_string.restype = ctypes.c_char_p
+        L.sf_last_hip_error.argtypes = []
+        L.sf_destroy.argtypes = [ctypes.POINTER(p)]
+        for name in EXPORTS:
+            if name != "sf_error_string":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc, where):
+    if rc != 0:
+        raise SfError(rc, where)
+
+
+def _ptr(x):
+    """Device address of a torch tensor, or an int address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def unit_of(t, dtype=None, bs=None):
+    """sf_unit of a torch tensor: dtype from the tensor, bs = elements per row.
+    MAXLOC pairs are passed explicitly (dtype=SF_F64_I32)."""
+    import torch
+    if dtype is None:
+        dtype = {torch.float64: SF_F64, torch.float32: SF_F32, torch.int32: SF_I32,
+                 torch.int64: SF_I64}[t.dtype]
+    if bs is None:
+        bs = 1 if t.dim() <= 1 else int(np.prod(t.shape[1:]))
+    return SfUnit(dtype, bs)
+
+
+class StarForest:
+    """One device's share of a star forest (PetscSF, Section 3.1).
+
+    ``iroot[i]`` is the root of leaf i, ``ilocal[i]`` its slot (None for a
+    contiguous leaf space), ``ranks[i]`` its segment label (None = one
+    segment)."""
+
+    def __init__(self, nroots, iroot, ilocal=None, ranks=None):
+        iroot = np.ascontiguousarray(iroot, dtype=np.int64)
+        n = iroot.size
+        nodes = np.zeros((n, 2), dtype=np.int64)
+        nodes[:, 1] = iroot
+        if ranks is not None:
+            nodes[:, 0] = np.asarray(ranks, dtype=np.int64)
+        il = None if ilocal is None else np.ascontiguousarray(ilocal, dtype=np.int64)
+        h = ctypes.c_void_p()
+        rc = lib().sf_create(int(nroots), n,
+                             None if il is None else il.ctypes.data_as(ctypes.c_void_p), SF_COPY_VALUES,
+                             nodes.ctypes.data_as(ctypes.c_void_p), SF_COPY_VALUES, ctypes.byref(h))
+        check(rc, "sf_create")
+        self.h = h
+        self.nroots = int(nroots)
+        self.nleaves = n
+
+    def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False):
+        o = SfSetupOpts(MODES.get(reduce_mode, reduce_mode), int(bool(use_patterns)),
+                        int(bool(analyze_only)), 0)
+        check(lib().sf_setup(self.h, ctypes.byref(o)), "sf_setup")
+        return self
+
+    def set_reduce_mode(self, mode):
+        check(lib().sf_set_reduce_mode(self.h, MODES.get(mode, mode)), "sf_set_reduce_mode")
+
+    # ------------------------------------------------------------ begin/end
+    def bcast_begin(self, unit, root, leaf, op="replace", stream=None):
+        check(lib().sf_bcast_begin(self.h, unit, _ptr(root), _ptr(leaf), OPS.get(op, op), _stream(stream)),
+              "sf_bcast_begin")
+
+    def bcast_end(self, unit, root, leaf, op="replace", stream=None):
+        check(lib().sf_bcast_end(self.h, unit, _ptr(root), _ptr(leaf), OPS.get(op, op), _stream(stream)),
+              "sf_bcast_end")
+
+    def reduce_begin(self, unit, leaf, root, op="sum", stream=None):
+        check(lib().sf_reduce_begin(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op), _stream(stream)),
+              "sf_reduce_begin")
+
+    def reduce_end(self, unit, leaf, root, op="sum", stream=None):
+        check(lib().sf_reduce_end(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op), _stream(stream)),
+              "sf_reduce_end")
+
+    def fetch_and_op_begin(self, unit, root, leaf, leafupdate, op="sum", stream=None):
+        check(lib().sf_fetch_and_op_begin(self.h, unit, _ptr(root), _ptr(leaf), _ptr(leafupdate),
+                                          OPS.get(op, op), _stream(stream)), "sf_fetch_and_op_begin")
+
+    def fetch_and_op_end(self, unit, root, leaf, leafupdate, op="sum", stream=None):
+        check(lib().sf_fetch_and_op_end(self.h, unit, _ptr(root), _ptr(leaf), _ptr(leafupdate),
+                                        OPS.get(op, op), _stream(stream)), "sf_fetch_and_op_end")
+
+    # ------------------------------------------------- begin + end helpers
+    def bcast(self, root, leaf, op="replace", unit=None, stream=None):
+        unit = unit or unit_of(root)
+        self.bcast_begin(unit, root, leaf, op, stream)
+        self.bcast_end(unit, root, leaf, op, stream)
+        return leaf
+
+    def reduce(self, leaf, root, op="sum", unit=None, stream=None):
+        unit = unit or unit_of(root)
+        self.reduce_begin(unit, leaf, root, op, stream)
+        self.reduce_end(unit, leaf, root, op, stream)
+        return root
+
+    def fetch_and_op(self, root, leaf, leafupdate, op="sum", unit=None, stream=None):
+        unit = unit or unit_of(root)
+        self.fetch_and_op_begin(unit, root, leaf, leafupdate, op, stream)
+        self.fetch_and_op_end(unit, root, leaf, leafupdate, op, stream)
+        return root, leafupdate
+
+    # ---------------------------------------------------------- inspection
+    def info(self):
+        inf = SfInfo()
+        check(lib().sf_get_info(self.h, ctypes.byref(inf)), "sf_get_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def segment(self, s):
+        seg = SfSegmentInfo()
+        check(lib().sf_get_segment(self.h, int(s), ctypes.byref(seg)), "sf_get_segment")
+        return {"rank": seg.rank, "nleaves": seg.nleaves, "root": seg.root.as_dict(),
+                "leaf": seg.leaf.as_dict()}
+
+    def destroy(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().sf_destroy(ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch of SF operations run in one persistent launch (sf_batch_*).
+    items: list of (StarForest, unit, kind, op, root_tensor, leaf_tensor)."""
+
+    def __init__(self, items):
+        arr = (SfBatchItem * len(items))()
+        self._keep = []
+        for k, (sf, unit, kind, op, root, leaf) in enumerate(items):
+            kind = {"bcast": SF_KIND_BCAST, "reduce": SF_KIND_REDUCE}.get(kind, kind)
+            arr[k] = SfBatchItem(sf.h.value, unit, kind, OPS.get(op, op), _ptr(root), _ptr(leaf))
+            self._keep.append((sf, root, leaf))
+        h = ctypes.c_void_p()
+        check(lib().sf_batch_create(len(items), arr, ctypes.byref(h)), "sf_batch_create")
+        self.h = h
+
+    def launch(self, stream=None):
+        check(lib().sf_batch_launch(self.h, _stream(stream)), "sf_batch_launch")
+
+    def launch_separate(self, stream=None):
+        check(lib().sf_batch_launch_separate(self.h, _stream(stream)), "sf_batch_launch_separate")
+
+    def graph_capture(self, mode=0, stream=None):
+        check(lib().sf_batch_graph_capture(self.h, int(mode), _stream(stream)), "sf_batch_graph_capture")
+
+    def graph_launch(self, stream=None):
+        check(lib().sf_batch_graph_launch(self.h, _stream(stream)), "sf_batch_graph_launch")
+
+    def autotune(self, cache_path=None, stream=None):
+        cp = None if cache_path is None else str(cache_path).encode()
+        check(lib().sf_batch_autotune(self.h, cp, _stream(stream)), "sf_batch_autotune")
+
+    def config(self):
+        lpt, tile, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        check(lib().sf_batch_get_config(self.h, ctypes.byref(lpt), ctypes.byref(tile), ctypes.byref(nt)),
+              "sf_batch_get_config")
+        return lpt.value, tile.value, nt.value
+
+    def set_config(self, lpt, tile):
+        check(lib().sf_batch_set_config(self.h, int(lpt), int(tile)), "sf_batch_set_config")
+
+    def destroy(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().sf_batch_destroy(ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,174 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+call that include/sf.h declares; graph validation and error codes; setup
+analysis (segments, pattern detection of Section 5.2, duplicate roots,
+degree classes) through ``analyze_only`` -- no device is touched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2102_13018_amd import inputs
+from paper_2102_13018_amd import sf as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "sf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(sf_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_exports():
+    assert sorted(S.EXPORTS) == header_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+
+
+def test_error_strings():
+    L = S.lib()
+    for code in S.ERRORS:
+        assert L.sf_error_string(code)
+    assert L.sf_error_string(0) == b"success"
+
+
+def create(nroots, iroot, ilocal=None, ranks=None):
+    return S.StarForest(nroots, iroot, ilocal, ranks)
+
+
+def test_validation_errors():
+    with pytest.raises(S.SfError) as e:
+        create(3, [0, 3])
+    assert e.value.code == -1
+    with pytest.raises(S.SfError) as e:
+        create(3, [0, -1])
+    assert e.value.code == -1
+    with pytest.raises(S.SfError) as e:
+        create(3, [0, 1], ilocal=[2, 2])
+    assert e.value.code == -2          # SF_ERR_DUP_LEAF: stars are disjoint
+    with pytest.raises(S.SfError) as e:
+        create(3, [0, 1], ilocal=[0, -4])
+    assert e.value.code == -1
+    with pytest.raises(S.SfError) as e:
+        create(-1, [])
+    assert e.value.code == -1
+    # OWN_POINTER is not supported
+    h = ctypes.c_void_p()
+    nodes = np.zeros((1, 2), np.int64)
+    rc = S.lib().sf_create(1, 1, None, S.SF_OWN_POINTER, nodes.ctypes.data_as(ctypes.c_void_p),
+                           S.SF_COPY_VALUES, ctypes.byref(h))
+    assert rc == -4
+
+
+def test_operations_before_setup_are_rejected():
+    sf = create(3, [0, 1, 1])
+    with pytest.raises(S.SfError) as e:
+        sf.bcast_begin(S.SfUnit(S.SF_F64, 1), 0x1000, 0x2000, "replace", 0)
+    assert e.value.code == -3
+    sf.setup(analyze_only=True)    # analysis only: still no device plan
+    with pytest.raises(S.SfError) as e:
+        sf.reduce_begin(S.SfUnit(S.SF_F64, 1), 0x1000, 0x2000, "sum", 0)
+    assert e.value.code == -3
+    with pytest.raises(S.SfError) as e:
+        sf.bcast_end(S.SfUnit(S.SF_F64, 1), 0x1000, 0x2000, "replace", 0)
+    assert e.value.code == -7      # end without begin
+
+
+def test_fig2_analysis():
+    g = inputs.fig2()
+    sf = create(g.nroots, g.iroot, g.ilocal, g.ranks).setup(analyze_only=True)
+    info = sf.info()
+    assert info["leafspace"] == 11 and info["nsegments"] == 3
+    assert info["has_dup_roots"] == 1 and info["max_degree"] == 3
+    assert info["nroots_touched"] == 7
+    seg = [sf.segment(s) for s in range(3)]
+    assert [s["nleaves"] for s in seg] == [4, 3, 3]
+    assert seg[0]["leaf"]["kind"] == S.SF_PATTERN_CONTIGUOUS          # slots 0..3
+    assert seg[1]["leaf"]["kind"] == S.SF_PATTERN_GENERIC             # slots 4, 5, 7
+
+
+def brute_indices(p, n):
+    """Enumerate start + i + sy*j + sz*k of a pattern in t order (Section 5.2)."""
+    if p["kind"] == S.SF_PATTERN_CONTIGUOUS:
+        return [p["start"] + t for t in range(n)]
+    out = []
+    for k in range(p["dz"]):
+        for j in range(p["dy"]):
+            for i in range(p["dx"]):
+                out.append(p["start"] + i + p["sy"] * j + p["sz"] * k)
+    return out
+
+
+@pytest.mark.parametrize("n", [4, 7, 16])
+def test_halo_patterns_detected(n):
+    g = inputs.halo3d(n)
+    sf = create(g.nroots, g.iroot, None, g.ranks).setup(analyze_only=True)
+    info = sf.info()
+    assert info["nsegments"] == 26
+    start = 0
+    for s in range(26):
+        seg = sf.segment(s)
+        m = seg["nleaves"]
+        assert seg["leaf"]["kind"] == S.SF_PATTERN_CONTIGUOUS and seg["leaf"]["start"] == start
+        assert seg["root"]["kind"] != S.SF_PATTERN_GENERIC, (s, seg)
+        assert brute_indices(seg["root"], m) == g.iroot[start:start + m].tolist()
+        start += m
+    # degrees: faces 1, edges 3, corners 7
+    deg = np.bincount(g.iroot, minlength=g.nroots)
+    assert info["max_degree"] == 7 and deg.max() == 7
+
+
+def test_pattern_detection_cases():
+    def one_segment(idx, nroots=None):
+        idx = np.asarray(idx, dtype=np.int64)
+        nroots = nroots or int(idx.max()) + 1
+        sf = create(nroots, idx).setup(analyze_only=True)
+        return sf.segment(0)["root"]
+    # contiguous
+    p = one_segment(np.arange(10, 50), 60)
+    assert p["kind"] == S.SF_PATTERN_CONTIGUOUS and p["start"] == 10
+    # strided: dx = 1
+    p = one_segment(np.arange(0, 300, 3))
+    assert p["kind"] == S.SF_PATTERN_3D and p["dx"] == 1 and p["sy"] == 3
+    # 3-D sub-block of a 10 x 8 x 6 box: start (2,1,1), size (4,3,2)
+    X, Y = 10, 8
+    blk = [2 + X * 1 + X * Y * 1 + i + X * j + X * Y * k for k in range(2) for j in range(3) for i in range(4)]
+    p = one_segment(blk, X * Y * 6)
+    assert (p["kind"], p["dx"], p["dy"], p["dz"], p["sy"], p["sz"]) == (S.SF_PATTERN_3D, 4, 3, 2, X, X * Y)
+    assert brute_indices(p, len(blk)) == blk
+    # near miss: one index perturbed -> generic
+    bad = list(blk)
+    bad[13] += 1
+    assert one_segment(bad, X * Y * 6)["kind"] == S.SF_PATTERN_GENERIC
+    # random -> generic
+    rng = np.random.default_rng(0)
+    assert one_segment(rng.integers(0, 1000, 500), 1000)["kind"] == S.SF_PATTERN_GENERIC
+
+
+def test_generic_path_when_patterns_off():
+    g = inputs.halo3d(6)
+    sf = create(g.nroots, g.iroot, None, g.ranks).setup(use_patterns=False, analyze_only=True)
+    assert sf.info()["nsegments"] == 26     # segments are still reported
+
+
+def test_hot_roots_of_zipf_graph():
+    g = inputs.spmv_ghost(seed=3, nroots=20000, nleaves=400000)
+    sf = create(g.nroots, g.iroot, None, g.ranks).setup(analyze_only=True)
+    info = sf.info()
+    deg = np.bincount(g.iroot, minlength=g.nroots)
+    assert info["max_degree"] == deg.max()
+    assert info["nroots_touched"] == int((deg > 0).sum())
+    assert info["nhot"] == min(2048, int((deg >= 1024).sum())) and info["nhot"] > 0
+    assert info["nsegments"] == 64
+
+
+def test_empty_graph_analysis():
+    sf = create(0, []).setup(analyze_only=True)
+    info = sf.info()
+    assert info["nleaves"] == 0 and info["nroots_touched"] == 0 and info["has_dup_roots"] == 0
