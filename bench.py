@@ -1,0 +1,391 @@
+#!/usr/bin/env python3
+"""Benchmark of the star-forest hot path on one MI355X.
+
+Workload: the unstructured SpMV-ghost SF (paper Section 4.1) at full size --
+nroots = 2,000,000, nleaves = 16,000,000, Zipf(1.1) root in-degree, 64
+neighbour segments -- with every operation of the hot path on it:
+SFBcast REPLACE (fp64), SFReduce SUM on the atomic and on the deterministic
+path (fp64, fp32), SFReduce MAX (fp64), MAXLOC (fp64,int32), SFFetchAndOp
+SUM (int64, multi-SF construction).  One step runs all of them once on data
+already resident in HBM.
+
+value = algorithmic bytes of a step (unit data + indices; roots counted once
+per distinct touched root) / measured time of a step, in GB/s.
+
+The remaining rows are measured after the timed loop and reported beside it:
+the 3-D halo pattern path vs the generic index path, the batched persistent
+launch vs per-SF launches (eager and graph-replayed), and the differentiable
+gather/scatter chain.  ``--profile-op NAME`` runs a single op (for rocprofv3).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def source_hash():
+    """Hash of the library sources: HBM counters taken on other sources are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2102_13018_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    the summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("_source_hash") != source_hash() or kernel not in d:
+        return None
+    return int(d[kernel]["fetch_bytes"] + d[kernel]["write_bytes"])
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-rows", action="store_true", help="skip the halo / batch / autograd rows")
+    p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
+    p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Op:
+    def __init__(self, name, fn, nbytes, kernel):
+        self.name, self.fn, self.nbytes, self.kernel = name, fn, nbytes, kernel
+        self.times = []
+
+
+def build_spmv_ops(torch, S, inputs, g):
+    """The ops of one step on the SpMV-ghost SF, with their algorithmic bytes."""
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(1234)
+    L, R = g.nleaves, g.nroots
+    deg = np.bincount(g.iroot, minlength=R)
+    Rt = int((deg > 0).sum())
+    idx = 4 * L                                     # iremote (ilocal is NULL)
+    t0 = time.time()
+    sf = S.StarForest(R, g.iroot, None, g.ranks).setup(reduce_mode="atomic")
+    log(f"setup of {L} leaves: {time.time() - t0:.2f} s, info {sf.info()}")
+
+    xr64 = torch.from_numpy(rng.standard_normal(R)).to(dev)
+    xl64 = torch.from_numpy(rng.standard_normal(L)).to(dev)
+    yl64 = torch.empty(L, dtype=torch.float64, device=dev)
+    xr32 = xr64.float()
+    xl32 = xl64.float()
+    pair = np.dtype([("v", "<f8"), ("i", "<i4"), ("pad", "<i4")])
+    lp = inputs.maxloc_leaves(rng, L)
+    rp = inputs.maxloc_roots(rng, R)
+    lpair = torch.from_numpy(lp.view(np.uint8)).to(dev)
+    rpair = torch.from_numpy(rp.view(np.uint8)).to(dev)
+    root0 = np.concatenate([[0], np.cumsum(deg)[:-1]]).astype(np.int64)
+    fr = torch.from_numpy(root0).to(dev)
+    fl = torch.ones(L, dtype=torch.int64, device=dev)
+    fu = torch.empty(L, dtype=torch.int64, device=dev)
+    u64, u32 = S.SfUnit(S.SF_F64, 1), S.SfUnit(S.SF_F32, 1)
+    upair, ui64 = S.SfUnit(S.SF_F64_I32, 1), S.SfUnit(S.SF_I64, 1)
+
+    def red(mode, leaf, root, op, unit):
+        def f():
+            sf.set_reduce_mode(mode)
+            sf.reduce(leaf, root, op, unit=unit)
+        return f
+
+    def fop(mode):
+        def f():
+            sf.set_reduce_mode(mode)
+            sf.fetch_and_op(fr, fl, fu, "sum", unit=ui64)
+        return f
+
+    b8 = lambda u: L * u + Rt * u + idx            # Bcast
+    r8 = lambda u: L * u + 2 * Rt * u + idx        # Reduce
+    f8 = lambda u: 2 * L * u + 2 * Rt * u + idx    # FetchAndOp
+    ops = [
+        Op("bcast_replace_f64", lambda: sf.bcast(xr64, yl64, "replace", unit=u64), b8(8), "k_bcast_move"),
+        Op("reduce_sum_f64_atomic", red("atomic", xl64, xr64, "sum", u64), r8(8), "k_reduce_atomic"),
+        Op("reduce_sum_f64_det", red("deterministic", xl64, xr64, "sum", u64), r8(8), "k_det_*"),
+        Op("reduce_sum_f32_det", red("deterministic", xl32, xr32, "sum", u32), r8(4), "k_det_*"),
+        Op("reduce_max_f64_atomic", red("atomic", xl64, xr64, "max", u64), r8(8), "k_reduce_atomic"),
+        Op("reduce_maxloc_det", red("deterministic", lpair, rpair, "maxloc", upair), r8(16), "k_det_*"),
+        Op("fetch_and_op_i64_det", fop("deterministic"), f8(8), "k_fop_*"),
+        Op("fetch_and_op_i64_atomic", fop("atomic"), f8(8), "k_fop_atomic_hot"),
+    ]
+    data = dict(xr64=xr64, xl64=xl64, deg=deg, Rt=Rt)
+    return sf, ops, data
+
+
+def time_ops(torch, ops, steps, warmup):
+    """Warm up, then time exactly `steps` steps; every op is bracketed by
+    events on the current stream (the stream the library launches on)."""
+    for _ in range(warmup):
+        for op in ops:
+            op.fn()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        for k, op in enumerate(ops):
+            ev[s][k][0].record()
+            op.fn()
+            ev[s][k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s in range(steps):
+        for k, op in enumerate(ops):
+            op.times.append(ev[s][k][0].elapsed_time(ev[s][k][1]))
+    return wall
+
+
+def cpu_baseline(g, budget_s=12.0):
+    """The oracle, as it stands, on the same SF: Bcast, Reduce SUM and
+    FetchAndOp (sequential C, one thread).  Runs ops until the budget is
+    spent (whole rounds); reports algorithmic bytes / time."""
+    import oracle
+    rng = np.random.default_rng(99)
+    L, R = g.nleaves, g.nroots
+    deg = np.bincount(g.iroot, minlength=R)
+    Rt = int((deg > 0).sum())
+    xr = rng.standard_normal(R)
+    xl = rng.standard_normal(L)
+    root0 = np.concatenate([[0], np.cumsum(deg)[:-1]]).astype(np.int64)
+    jobs = [("bcast_replace_f64", lambda: oracle.bcast(R, g.iroot, None, xr, xl), L * 8 + Rt * 8 + 4 * L),
+            ("reduce_sum_f64", lambda: oracle.reduce(R, g.iroot, None, xl, xr), L * 8 + 2 * Rt * 8 + 4 * L),
+            ("fetch_and_op_i64", lambda: oracle.fetch_and_op(R, g.iroot, None, root0, np.ones(L, np.int64),
+                                                             np.zeros(L, np.int64)),
+             2 * L * 8 + 2 * Rt * 8 + 4 * L)]
+    tot_b, tot_t, rounds = 0, 0.0, 0
+    while tot_t < budget_s:
+        for name, fn, nb in jobs:
+            t0 = time.perf_counter()
+            fn()
+            tot_t += time.perf_counter() - t0
+            tot_b += nb
+        rounds += 1
+    return {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rounds} rounds of (" + ", ".join(j[0] for j in jobs) + ") on the full spmv_ghost SF, "
+                      f"sequential C oracle, {tot_t:.1f} s of CPU time"}
+
+
+def halo_row(torch, S, inputs, steps):
+    g = inputs.halo3d(256)
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(5)
+    out = {}
+    for bs in (1, 3):
+        root = torch.from_numpy(rng.standard_normal((g.nroots, bs))).to(dev)
+        leaf = torch.empty((g.nleaves, bs), dtype=torch.float64, device=dev)
+        u = S.SfUnit(S.SF_F64, bs)
+        Rt = g.nroots - 0  # every owned boundary point; count below
+        deg = np.bincount(g.iroot, minlength=g.nroots)
+        Rt = int((deg > 0).sum())
+        for pat in (True, False):
+            sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="deterministic", use_patterns=pat)
+            idx = 0 if pat else 4 * g.nleaves
+            for kind in ("bcast", "reduce"):
+                fn = (lambda: sf.bcast(root, leaf, "replace", unit=u)) if kind == "bcast" else \
+                    (lambda: sf.reduce(leaf, root, "sum", unit=u))
+                nb = g.nleaves * 8 * bs + (1 if kind == "bcast" else 2) * Rt * 8 * bs + idx
+                op = Op(kind, fn, nb, "")
+                time_ops(torch, [op], steps, 3)
+                ms = float(np.median(op.times))
+                out[f"{kind}_bs{bs}_{'pattern' if pat else 'generic'}"] = {
+                    "us": round(ms * 1e3, 2), "GBps": round(nb / ms / 1e6, 1)}
+    return {"workload": "halo3d(n=256, 26 segments, 396296 ghost leaves)", "ops": out}
+
+
+def batch_row(torch, S, inputs, steps):
+    items = inputs.batch_mix(seed=4)
+    dev = torch.device("cuda")
+    bitems, keep, nbytes = [], [], 0
+    tdt = {np.dtype(np.float64): (torch.float64, S.SF_F64, 8), np.dtype(np.float32): (torch.float32, S.SF_F32, 4),
+           np.dtype(np.int32): (torch.int32, S.SF_I32, 4)}
+    for it in items:
+        g = it["graph"]
+        rng = np.random.default_rng(it["seed"])
+        tt, sd, es = tdt[it["dtype"]]
+        bs = it["bs"]
+        sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="atomic")
+        root = torch.from_numpy(inputs.unit_data(rng, g.nroots, bs, it["dtype"])).to(dev)
+        leaf = torch.from_numpy(inputs.unit_data(rng, g.nleaves, bs, it["dtype"])).to(dev)
+        deg = np.bincount(g.iroot, minlength=g.nroots)
+        Rt = int((deg > 0).sum())
+        u = es * bs
+        nbytes += g.nleaves * u + (1 if it["kind"] == "bcast" else 2) * Rt * u + 4 * g.nleaves
+        bitems.append((sf, S.SfUnit(sd, bs), it["kind"], it["op"], root, leaf))
+        keep.append(sf)
+    batch = S.Batch(bitems)
+    batch.autotune(None)
+    cfg = batch.config()
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        batch.graph_capture(0, stream)
+        res_graph_persist = Op("graph_persistent", lambda: batch.graph_launch(stream), nbytes, "")
+        torch.cuda.synchronize()
+        for name, fn in (("persistent", lambda: batch.launch(stream)),
+                         ("separate", lambda: batch.launch_separate(stream))):
+            op = Op(name, fn, nbytes, "")
+            time_ops(torch, [op], steps, 3)
+            res[name] = op
+        time_ops(torch, [res_graph_persist], steps, 3)
+        res["graph_persistent"] = res_graph_persist
+        batch.graph_capture(1, stream)
+        op = Op("graph_separate", lambda: batch.graph_launch(stream), nbytes, "")
+        time_ops(torch, [op], steps, 3)
+        res["graph_separate"] = op
+    # host wall time of one launch-to-sync, median over reps
+    wall = {}
+    for name, fn in (("persistent", lambda: batch.launch(stream)), ("separate", lambda: batch.launch_separate(stream))):
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            fn()
+            stream.synchronize()
+            ts.append(time.perf_counter() - t0)
+        wall[name] = round(float(np.median(ts)) * 1e6, 1)
+    out = {k: {"us": round(float(np.median(v.times)) * 1e3, 1),
+               "GBps": round(nbytes / float(np.median(v.times)) / 1e6, 1)} for k, v in res.items()}
+    return {"workload": f"batch_mix(64 SFs, {sum(i['graph'].nleaves for i in items)} leaves)",
+            "alg_bytes": nbytes, "autotuned": {"lpt": cfg[0], "tile": cfg[1], "tiles": cfg[2]},
+            "device": out, "host_wall_us": wall}
+
+
+def autograd_row(torch, S, inputs, steps):
+    from paper_2102_13018_amd import autograd as A
+    g = inputs.knn_graph(seed=5)
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(6)
+    sf = S.StarForest(g.nroots, g.iroot, None, None).setup(reduce_mode="deterministic")
+    h = torch.from_numpy(rng.standard_normal((g.nroots, 16)).astype(np.float32)).to(dev).requires_grad_(True)
+    a = [torch.from_numpy((rng.standard_normal(g.nleaves) / np.sqrt(8)).astype(np.float32)).to(dev)
+         for _ in range(3)]
+    G = torch.from_numpy(rng.standard_normal((g.nroots, 16)).astype(np.float32)).to(dev)
+    deg = np.bincount(g.iroot, minlength=g.nroots)
+    Rt = int((deg > 0).sum())
+    L = g.nleaves
+
+    def step():
+        loss = A.chain_loss(sf, h, a, G, checkpoint=True)
+        loss.backward()
+        h.grad = None
+
+    op = Op("chain", step, 0, "")
+    time_ops(torch, [op], max(3, steps // 4), 2)
+    # per-layer SF traffic: forward Bcast + Reduce, backward Reduce + Bcast,
+    # plus the checkpoint recompute of the forward pair
+    u = 64
+    bc = L * u + Rt * u + 4 * L
+    rd = L * u + 2 * Rt * u + 4 * L
+    sf_bytes = 3 * (2 * (bc + rd) + (bc + rd))
+    ms = float(np.median(op.times))
+    return {"workload": f"knn(npoints={g.nroots}, k=8) fp32 x16, 3-layer checkpointed chain",
+            "step_us": round(ms * 1e3, 1), "sf_alg_bytes": sf_bytes,
+            "sf_GBps_lower_bound": round(sf_bytes / ms / 1e6, 1)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2102_13018_amd import inputs
+    from paper_2102_13018_amd import sf as S
+    S.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_bytes:
+        # a plain device copy of known size: the scale of the HBM counters
+        n = args.copy_bytes // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied 3 x {args.copy_bytes} bytes")
+        del a, b
+        if not args.profile_op:
+            return
+
+    t0 = time.time()
+    g = inputs.spmv_ghost(seed=3)
+    log(f"generated spmv_ghost in {time.time() - t0:.1f} s")
+    sf, ops, data = build_spmv_ops(torch, S, inputs, g)
+    if args.profile_op:
+        names = args.profile_op.split(",")
+        ops = [o for o in ops if o.name in names]
+        assert len(ops) == len(names), f"unknown op in {args.profile_op}"
+        time_ops(torch, ops, args.steps, args.warmup)
+        for o in ops:
+            log(f"{o.name}: median {np.median(o.times) * 1e3:.1f} us over {len(o.times)} launches")
+        return
+
+    torch.cuda.synchronize()
+    wall = time_ops(torch, ops, args.steps, args.warmup)
+    step_bytes = sum(o.nbytes for o in ops)
+    ms_per_step = wall * 1e3 / args.steps
+    value = step_bytes / (wall / args.steps) / 1e9
+    per_op = {}
+    for o in ops:
+        med = float(np.median(o.times))
+        per_op[o.name] = {"us": round(med * 1e3, 1), "alg_MB": round(o.nbytes / 1e6, 1),
+                          "GBps": round(o.nbytes / med / 1e6, 1),
+                          "frac_peak": round(o.nbytes / med / 1e6 / HBM_PEAK_GBS, 4)}
+        log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
+    # dominant single-kernel op (largest share of step time)
+    single = [o for o in ops if o.kernel in ("k_bcast_move", "k_reduce_atomic", "k_fop_atomic_hot")]
+    dom = max(single, key=lambda o: float(np.mean(o.times)))
+    avg_ms = float(np.mean(dom.times))
+    roofline = {"bound": "hbm", "kernel": dom.kernel, "op": dom.name,
+                "achieved": round(dom.nbytes / avg_ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom.nbytes / avg_ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.kernel),
+                "alg_bytes_per_launch": dom.nbytes,
+                "avg_launch_us": round(avg_ms * 1e3, 1)}
+    out = {"metric": "effective HBM GB/s (unit data + indices) for SFBcast/SFReduce vs peak; batched vs per-SF time",
+           "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
+                      "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
+                      "parallelism": "single-gpu"},
+           "ops": per_op, "roofline": roofline}
+    if not args.no_rows:
+        for name, fn in (("halo", halo_row), ("batch", batch_row), ("autograd", autograd_row)):
+            try:
+                out[f"row_{name}"] = fn(torch, S, inputs, args.steps)
+            except Exception as e:  # a row that cannot run is reported, not hidden
+                out[f"row_{name}"] = {"error": repr(e)}
+            log(f"row {name}: {out[f'row_{name}']}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

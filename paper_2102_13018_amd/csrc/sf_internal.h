@@ -16,7 +16,8 @@ namespace sfi {
 
 // ------------------------------------------------------------------ limits
 constexpr int kBlock = 256;          // threads per block of the stream kernels
-constexpr int kTileLeaves = 2048;    // leaves per work tile of the stream kernels
+constexpr int kTileLeaves = 2048;    // largest work tile of the stream kernels (leaves)
+constexpr int kTileMin = 256;        // smallest work tile
 constexpr int kChunkLPT = 4;         // leaves per lane of the wave-chunk reduction
 constexpr int kChunk = 64 * kChunkLPT;  // leaves per aligned chunk (power of two)
 constexpr int kSmallMaxDeg = 32;     // largest degree of the per-thread classes
@@ -68,6 +69,7 @@ struct HostPlan {
   // segments and tiles of the stream kernels
   std::vector<DevSegment> dsegs;
   std::vector<DevTile> tiles;
+  int32_t tile_leaves = kTileLeaves;  // leaves per tile of this SF
   std::vector<int32_t> ridx;      // root index per processed leaf (generic root sides)
   std::vector<int32_t> ridx_hot;  // same, hot roots encoded as -(h+1)
   std::vector<int32_t> lidx;      // leaf slot per processed leaf (generic leaf sides)

@@ -416,32 +416,55 @@ __global__ __launch_bounds__(kBlock) void k_fop_chunk_sum(const DevChunk *__rest
   }
 }
 
-// Large roots, pass 2: one wavefront per large root turns its chunk sums
-// into chunk bases (root value + exclusive prefix) and writes the final root.
+// Large roots, pass 2: one block per large root turns its chunk sums into
+// chunk bases (root value + exclusive prefix) and writes the final root.
+// Each iteration scans kBlock*4 chunk sums: 4 per thread in registers, the
+// threads' totals across the wavefront with shuffles, the 4 wavefront totals
+// through LDS.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fop_root_scan(const int32_t *__restrict__ first, int nlarge,
                                                           const DevChunk *__restrict__ chunks, T *__restrict__ sums,
                                                           T *__restrict__ root, int bs) {
-  const int lane = threadIdx.x & 63;
-  const int wid = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
-  if (wid >= nlarge) return;
-  const int c0 = first[wid], c1 = first[wid + 1];
+  __shared__ T wtot[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x;
+  if (k >= nlarge) return;
+  const int c0 = first[k], c1 = first[k + 1];
   const int32_t r = chunks[c0].dst;
   for (int c = 0; c < bs; c++) {
     T carry = root[(int64_t)r * bs + c];
-    for (int base = c0; base < c1; base += 64) {
-      const int k = base + lane;
-      const T x = k < c1 ? sums[(int64_t)k * bs + c] : T(0);
-      T inc = x;
+    for (int base = c0; base < c1; base += kBlock * 4) {
+      T x[4];
+      T s = T(0);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int i = base + threadIdx.x * 4 + j;
+        x[j] = i < c1 ? sums[(int64_t)i * bs + c] : T(0);
+        s = Op<OP_SUM, T>::apply(s, x[j]);
+      }
+      T inc = s;
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
         const T o = shfl_up(inc, d);
         if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
       }
-      if (k < c1) sums[(int64_t)k * bs + c] = Op<OP_SUM, T>::apply(carry, wrap_sub(inc, x));
-      carry = Op<OP_SUM, T>::apply(carry, __shfl(inc, 63));
+      if (lane == 63) wtot[wv] = inc;
+      __syncthreads();
+      T before = carry;
+      for (int w = 0; w < wv; w++) before = Op<OP_SUM, T>::apply(before, wtot[w]);
+      T total = carry;
+      for (int w = 0; w < kBlock / 64; w++) total = Op<OP_SUM, T>::apply(total, wtot[w]);
+      T a = Op<OP_SUM, T>::apply(before, wrap_sub(inc, s));
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int i = base + threadIdx.x * 4 + j;
+        if (i < c1) sums[(int64_t)i * bs + c] = a;
+        a = Op<OP_SUM, T>::apply(a, x[j]);
+      }
+      carry = total;
+      __syncthreads();
     }
-    if (lane == 0) root[(int64_t)r * bs + c] = carry;
+    if (threadIdx.x == 0) root[(int64_t)r * bs + c] = carry;
   }
 }
 
@@ -736,7 +759,7 @@ static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream
     T *sums = (T *)sf->scratch;
     hipLaunchKernelGGL((k_fop_chunk_sum<T>), dim3(nblocks((int64_t)nch * 64)), dim3(kBlock), 0, st, d.fo_chunks, nch,
                        d.sl, leaf, sums, bs);
-    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3(nblocks((int64_t)nlarge * 64)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3(nlarge), dim3(kBlock), 0, st,
                        d.fo_root_first, nlarge, d.fo_chunks, sums, root, bs);
     hipLaunchKernelGGL((k_fop_chunk_apply<T>), dim3(nblocks((int64_t)nch * 64)), dim3(kBlock), 0, st, d.fo_chunks, nch,
                        d.sl, leaf, sums, upd, bs);

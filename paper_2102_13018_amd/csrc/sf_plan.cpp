@@ -197,7 +197,11 @@ int analyze(sf_s *sf) {
     for (size_t h = 0; h < cand.size(); h++) hot_of[cand[h]] = (int32_t)h;
   }
 
-  // ---- index arrays and tiles
+  // ---- index arrays and tiles.  Tiles shrink for small SFs so that the
+  // grid still has about four blocks per compute unit.
+  int32_t tl = kTileLeaves;
+  while (tl > kTileMin && L / tl < 1024) tl /= 2;
+  hp.tile_leaves = tl;
   const bool want_hot = !hp.hot_roots.empty();
   for (size_t s = 0; s < lay.size(); s++) {
     const Lay &ly = lay[s];
@@ -221,8 +225,8 @@ int analyze(sf_s *sf) {
       for (int64_t t = 0; t < n; t++) hp.lidx.push_back((int32_t)slot(member(t)));
     }
     hp.dsegs.push_back(d);
-    for (int64_t t0 = 0; t0 < n; t0 += kTileLeaves)
-      hp.tiles.push_back({(int32_t)s, (int32_t)t0, (int32_t)std::min<int64_t>(n, t0 + kTileLeaves), 0});
+    for (int64_t t0 = 0; t0 < n; t0 += tl)
+      hp.tiles.push_back({(int32_t)s, (int32_t)t0, (int32_t)std::min<int64_t>(n, t0 + tl), 0});
   }
   if (want_hot && hp.ridx_hot.empty()) hp.hot_roots.clear();
 
