@@ -90,7 +90,8 @@ typedef struct {
   int32_t reduce_mode;  /* sf_reduce_mode, default AUTO */
   int32_t use_patterns; /* 1 (default): detect contiguous / 3-D sub-block index patterns */
   int32_t analyze_only; /* 1: host analysis only, no device memory (for inspection) */
-  int32_t reserved;
+  int32_t partition;    /* deterministic path through bucket-major scratch: 0 auto (SFs of
+                           2^20 leaves or more), 1 always, 2 never; results are identical */
 } sf_setup_opts;
 
 /* Index pattern of one side of one segment (Section 5.2): index(t) for the
@@ -173,7 +174,7 @@ int sf_bcast_begin(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, 
 int sf_bcast_end(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, int32_t op,
                  hipStream_t stream);
 
-/* SFReduce (Section 3.2, item 1, "vice versa"): leaves -> root, the root's
+/* SFReduce (Section 3.2, item 1, the reverse direction): leaves -> root, the root's
  * own value taking part (Section 4.1 adds B^T x back onto y).  Roots without
  * leaves are not touched.  REPLACE: the last leaf in leaf order wins
  * (deterministic mode; in atomic mode some leaf wins).  MAXLOC: larger

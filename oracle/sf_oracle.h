@@ -9,8 +9,8 @@
  *   leaf i in [0, nleaves) lives at slot l_i = ilocal[i] (or i when ilocal is
  *   NULL) and is connected to root r_i = iroot[i] in [0, nroots)
  *   (Section 3.1, PetscSFSetGraph).  L_r = { i : r_i = r } in ascending i.
- *   Data are arrays of "units"; a unit is bs contiguous elements of one
- *   type (Section 3.2: "unit is the data type of the tree vertices").
+ *   Data are arrays of units; a unit is bs contiguous elements of one
+ *   type (Section 3.2: the unit argument is the type of a vertex's data).
  *
  * Arithmetic is carried out in the unit's own type, since the unit (an MPI
  * datatype in the paper) fixes the precision of MPI_SUM and friends.  Build
@@ -44,7 +44,7 @@ enum { ORC_PW_TOPDOWN = 0, ORC_PW_BOTTOMUP = 1 };
 int orc_bcast(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
               int dtype, int bs, int op, const void *rootdata, void *leafdata);
 
-/* SFReduce (Section 3.2, item 1, "vice versa"): for every root r with a
+/* SFReduce (Section 3.2, item 1, leaves to roots): for every root r with a
  * non-empty L_r, combine the root's value with the values of its leaves:
  *   FP SUM : root[r] = root[r] + PW(leaf[l_i] : i in L_r)  (pairwise, leaf order)
  *   int SUM: two's-complement wrap-around

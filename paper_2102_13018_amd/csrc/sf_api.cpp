@@ -80,6 +80,7 @@ extern "C" int sf_setup(sf_t sf, const sf_setup_opts *opts) {
   o.use_patterns = 1;
   if (opts) o = *opts;
   if (o.reduce_mode < SF_REDUCE_AUTO || o.reduce_mode > SF_REDUCE_DETERMINISTIC) return SF_ERR_ARG;
+  if (o.partition < 0 || o.partition > 2) return SF_ERR_ARG;
   sf->opts = o;
   sf->reduce_mode = o.reduce_mode;
   sf->setup = false;

@@ -360,3 +360,11 @@ namespace sfi {
 __device__ __forceinline__ int32_t wrap_sub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
 __device__ __forceinline__ int64_t wrap_sub(int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }
 }  // namespace sfi
+
+namespace sfi {
+// Launchers of the partitioned deterministic path (sf_partition.hip).
+template <typename T, int OP>
+int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st);
+template <typename T>
+int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st);
+}  // namespace sfi

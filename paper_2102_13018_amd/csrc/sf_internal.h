@@ -22,9 +22,19 @@ constexpr int kChunkLPT = 4;         // leaves per lane of the wave-chunk reduct
 constexpr int kChunk = 64 * kChunkLPT;  // leaves per aligned chunk (power of two)
 constexpr int kSmallMaxDeg = 32;     // largest degree of the per-thread classes
 constexpr int kNumClasses = 6;       // degree classes 1, 2, 4, 8, 16, 32
-constexpr int kHotMax = 2048;        // roots aggregated in LDS by the atomic path
-constexpr int kHotLdsBytes = 32768;  // LDS budget for those accumulators
-constexpr int kPersistBlocks = 2048; // grid of the persistent atomic kernels
+constexpr int kHotMax = 8192;        // candidate roots for LDS aggregation on the atomic path
+constexpr int kHotMinDeg = 64;       // smallest degree of such a candidate
+constexpr int kHotLdsBytes = 32768;  // LDS budget for the accumulators, default
+constexpr int kPersistBlocks = 1024; // grid of the persistent atomic kernels, default
+constexpr int kStageBytes = 32768;   // LDS staging of a work tile's leaf units (partitioned path)
+// Partitioned deterministic path: leaves are first scattered into
+// bucket-major scratch (pass A), then reduced window by window (pass B) with
+// the windows of one bucket scheduled on one XCD, so that the gathers of
+// pass B hit that XCD's L2.
+constexpr int kXcd = 8;              // XCDs of an MI355X (work-group i runs on XCD i % 8)
+constexpr int kWindow = 2048;        // sorted leaves per window (one block), default
+constexpr int kBucketWindows = 32;   // windows per bucket, default
+constexpr int64_t kPartitionMin = 1 << 20;  // automatic partitioning from this many leaves
 
 // --------------------------------------------------------- device structs
 // Pattern of one side of a segment: index(t) = start + i + sy*j + sz*k with
@@ -37,13 +47,18 @@ struct DevSegment {
   int32_t n;        // leaves in the segment
   int32_t roff;     // offset of the segment in the root-index array (generic root side)
   int32_t loff;     // offset of the segment in the leaf-slot array (generic leaf side)
-  int32_t pad;
+  int32_t pbase;    // processing position of the segment's first leaf
   DevPattern root;
   DevPattern leaf;
 };
 
 struct DevTile {  // leaves [t0, t1) of segment seg
   int32_t seg, t0, t1, pad;
+};
+
+struct DevWindow {  // items of one window of the partitioned path
+  int32_t small0, small1;  // range in the small-root item list
+  int32_t big0, big1;      // range in the chunk item list
 };
 
 struct DevChunk {  // one aligned chunk of a root's (sorted) value list
@@ -73,7 +88,8 @@ struct HostPlan {
   std::vector<int32_t> ridx;      // root index per processed leaf (generic root sides)
   std::vector<int32_t> ridx_hot;  // same, hot roots encoded as -(h+1)
   std::vector<int32_t> lidx;      // leaf slot per processed leaf (generic leaf sides)
-  std::vector<int32_t> hot_roots; // root id of hot slot h
+  std::vector<int32_t> hot_roots; // root id of hot slot h, by decreasing degree
+  std::vector<int64_t> hot_deg;   // degree of hot slot h
   // root-sorted lists
   std::vector<int32_t> troot;     // touched roots, ascending
   std::vector<int32_t> toff;      // [ntouched+1] offsets into sl
@@ -85,6 +101,17 @@ struct HostPlan {
   // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
   std::vector<DevChunk> fo_chunks;
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
+  // partitioned deterministic path (empty when not used)
+  bool part = false;
+  std::vector<int32_t> pp_dst;    // [L] scratch slot of the p-th processed leaf
+  std::vector<int32_t> pa_dst;    // [L] per work tile, the tile's scratch slots in increasing order
+  std::vector<uint16_t> pa_loc;   // [L] tile-local processing offset of the leaf written to pa_dst[j]
+  std::vector<int32_t> pp_src;    // [L] scratch slot of the g-th sorted leaf (pass B)
+  std::vector<DevWindow> pp_win;
+  std::vector<int32_t> pp_small;  // touched-root ordinals of degree <= kSmallMaxDeg, window-major
+  std::vector<int32_t> pp_big;    // level-0 chunk ordinals, window-major
+  std::vector<int32_t> pp_sched;  // [kXcd * pp_jmax] window ids per XCD, -1 = none
+  int32_t pp_jmax = 0;
 };
 
 // Device copy of the plan: one allocation, typed views into it.
@@ -100,6 +127,10 @@ struct DevPlan {
   std::vector<DevChunk *> levels;
   DevChunk *fo_chunks = nullptr;
   int32_t *fo_root_first = nullptr;
+  int32_t *pa_dst = nullptr;
+  uint16_t *pa_loc = nullptr;
+  int32_t *pp_src = nullptr, *pp_small = nullptr, *pp_big = nullptr, *pp_sched = nullptr;
+  DevWindow *pp_win = nullptr;
 };
 
 struct Pending {
@@ -149,4 +180,12 @@ int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, 
 int launch_fetch_and_op(sf_s *sf, sf_unit unit, void *root, const void *leaf, void *upd, int op,
                         hipStream_t st);
 int elem_size(int32_t dtype);
+// launch shape of the persistent atomic kernels: grid size and the number of
+// hot roots (a prefix of hot_roots) that a block aggregates in LDS
+struct AtomicShape {
+  int grid;
+  int nhot_lds;
+  size_t lds_bytes;
+};
+AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes);
 }  // namespace sfi

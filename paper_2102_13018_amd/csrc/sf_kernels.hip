@@ -18,7 +18,7 @@
 //    leaves in leaf order, so the result is the same for any launch shape.
 #include <algorithm>
 
-#include "sf_device.h"
+#include "sf_det_kernels.h"
 
 namespace sfi {
 
@@ -239,54 +239,6 @@ __global__ __launch_bounds__(kBlock) void k_det_small(const int32_t *__restrict_
   st(rp, Op<OP, T>::apply(ld(rp), x[0]));
 }
 
-// One wavefront per aligned chunk of at most kChunk elements.  Lane l holds
-// elements [l*LPT, (l+1)*LPT) of the chunk; the lane's block is reduced in
-// registers, then lanes combine at distances 1, 2, ..., 32 -- all nodes of
-// the canonical pairwise tree of the chunk.  Level 0 reads leaves through
-// the sorted slot list; later levels read the previous level's results.
-template <typename T, int OP>
-__global__ __launch_bounds__(kBlock) void k_det_chunk(const DevChunk *__restrict__ chunks, int nchunks,
-                                                      const int32_t *__restrict__ sl, const T *__restrict__ src,
-                                                      T *__restrict__ dst_seq, T *__restrict__ root, int bs) {
-  constexpr int LPT = kChunkLPT;
-  const int lane = threadIdx.x & 63;
-  const int wid = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
-  if (wid >= nchunks) return;
-  const DevChunk ch = chunks[wid];
-  int32_t idx[LPT];
-#pragma unroll
-  for (int s = 0; s < LPT; s++) {
-    const int e = lane * LPT + s;
-    idx[s] = e < ch.n ? (sl ? sl[ch.src + e] : ch.src + e) : 0;
-  }
-  const int m = ch.n - lane * LPT;  // valid elements of this lane (may be <= 0)
-  for (int c = 0; c < bs; c++) {
-    T x[LPT];
-#pragma unroll
-    for (int s = 0; s < LPT; s++)
-      if (s < m) x[s] = ld(src + (int64_t)idx[s] * bs + c);
-#pragma unroll
-    for (int d = 1; d < LPT; d *= 2)
-#pragma unroll
-      for (int p = 0; p + d < LPT; p += 2 * d)
-        if (p + d < m) x[p] = Op<OP, T>::apply(x[p], x[p + d]);
-    T v = x[0];
-#pragma unroll
-    for (int d = 1; d < 64; d *= 2) {
-      const T o = shfl_down(v, d);
-      if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < ch.n) v = Op<OP, T>::apply(v, o);
-    }
-    if (lane == 0) {
-      if (ch.dst < 0) {
-        T *rp = root + (int64_t)(-ch.dst - 1) * bs + c;
-        st(rp, Op<OP, T>::apply(ld(rp), v));
-      } else {
-        st(dst_seq + (int64_t)ch.dst * bs + c, v);
-      }
-    }
-  }
-}
-
 // Reduce REPLACE with duplicate roots: the last leaf in leaf order wins.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_det_replace(const int32_t *__restrict__ troot, int ntouched,
@@ -319,15 +271,16 @@ __global__ __launch_bounds__(kBlock) void k_fop_atomic(const DevSegment *__restr
   }
 }
 
-// Atomic path with block aggregation of hot roots.  Pass A: ordinary leaves
-// fetch-and-add on the device; leaves of hot roots only add into an LDS
-// total.  The block then reserves each total with ONE device fetch-and-add,
-// which returns the base of the block's run of partial values.  Pass B: the
-// hot leaves fetch-and-add on that LDS base, obtaining consecutive partial
-// values of the root (a valid per-root order of the n reductions).
+// Atomic path with block aggregation of hot roots, over a persistent grid.
+// Pass 1 over the block's tiles: ordinary leaves fetch-and-add on the
+// device; leaves of hot roots only add into an LDS total.  The block then
+// reserves each total with ONE device fetch-and-add, which returns the base
+// of the block's run of partial values.  Pass 2 over the same tiles: the hot
+// leaves fetch-and-add on that LDS base, obtaining consecutive partial
+// values of the root (a valid per-root order of the reductions).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fop_atomic_hot(const DevSegment *__restrict__ segs,
-                                                           const DevTile *__restrict__ tiles,
+                                                           const DevTile *__restrict__ tiles, int ntiles,
                                                            const int32_t *__restrict__ ridx_hot,
                                                            const int32_t *__restrict__ lidx,
                                                            const int32_t *__restrict__ hot_roots, int nhot_lds,
@@ -339,34 +292,41 @@ __global__ __launch_bounds__(kBlock) void k_fop_atomic_hot(const DevSegment *__r
   for (int k = threadIdx.x; k < nhot_lds * bs; k += kBlock) acc[k] = T(0);
   for (int k = threadIdx.x; k < nhot_lds; k += kBlock) touched[k] = 0;
   __syncthreads();
-  const DevTile tl = tiles[blockIdx.x];
-  const DevSegment sg = segs[tl.seg];
-  const int items = (tl.t1 - tl.t0) * bs;
-  for (int q = threadIdx.x; q < items; q += kBlock) {
-    const int t = tl.t0 + q / bs;
-    const int c = q % bs;
-    const int32_t r = seg_root(sg, ridx_hot, t);
-    const int64_t l = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
-    if (r >= 0) {
-      upd[l] = fetch_add_g(root + (int64_t)r * bs + c, leaf[l]);
-    } else if (-r - 1 >= nhot_lds) {
-      upd[l] = fetch_add_g(root + (int64_t)hot_roots[-r - 1] * bs + c, leaf[l]);
-    } else {
-      __hip_atomic_fetch_add(acc + (-r - 1) * bs + c, leaf[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      touched[-r - 1] = 1;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const DevTile tl = tiles[tile];
+    const DevSegment sg = segs[tl.seg];
+    const int items = (tl.t1 - tl.t0) * bs;
+    for (int q = threadIdx.x; q < items; q += kBlock) {
+      const int t = tl.t0 + q / bs;
+      const int c = q % bs;
+      const int32_t r = seg_root(sg, ridx_hot, t);
+      const int64_t l = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
+      if (r >= 0) {
+        upd[l] = fetch_add_g(root + (int64_t)r * bs + c, leaf[l]);
+      } else if (-r - 1 >= nhot_lds) {
+        upd[l] = fetch_add_g(root + (int64_t)hot_roots[-r - 1] * bs + c, leaf[l]);
+      } else {
+        __hip_atomic_fetch_add(acc + (-r - 1) * bs + c, leaf[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        touched[-r - 1] = 1;
+      }
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nhot_lds * bs; k += kBlock)
     if (touched[k / bs]) acc[k] = fetch_add_g(root + (int64_t)hot_roots[k / bs] * bs + k % bs, acc[k]);
   __syncthreads();
-  for (int q = threadIdx.x; q < items; q += kBlock) {
-    const int t = tl.t0 + q / bs;
-    const int32_t r = seg_root(sg, ridx_hot, t);
-    if (r >= 0 || -r - 1 >= nhot_lds) continue;
-    const int c = q % bs;
-    const int64_t l = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
-    upd[l] = __hip_atomic_fetch_add(acc + (-r - 1) * bs + c, leaf[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const DevTile tl = tiles[tile];
+    const DevSegment sg = segs[tl.seg];
+    const int items = (tl.t1 - tl.t0) * bs;
+    for (int q = threadIdx.x; q < items; q += kBlock) {
+      const int t = tl.t0 + q / bs;
+      const int32_t r = seg_root(sg, ridx_hot, t);
+      if (r >= 0 || -r - 1 >= nhot_lds) continue;
+      const int c = q % bs;
+      const int64_t l = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
+      upd[l] = __hip_atomic_fetch_add(acc + (-r - 1) * bs + c, leaf[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
 }
 
@@ -413,58 +373,6 @@ __global__ __launch_bounds__(kBlock) void k_fop_chunk_sum(const DevChunk *__rest
 #pragma unroll
     for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
     if (lane == 0) sums[(int64_t)wid * bs + c] = a;
-  }
-}
-
-// Large roots, pass 2: one block per large root turns its chunk sums into
-// chunk bases (root value + exclusive prefix) and writes the final root.
-// Each iteration scans kBlock*4 chunk sums: 4 per thread in registers, the
-// threads' totals across the wavefront with shuffles, the 4 wavefront totals
-// through LDS.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fop_root_scan(const int32_t *__restrict__ first, int nlarge,
-                                                          const DevChunk *__restrict__ chunks, T *__restrict__ sums,
-                                                          T *__restrict__ root, int bs) {
-  __shared__ T wtot[kBlock / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int k = blockIdx.x;
-  if (k >= nlarge) return;
-  const int c0 = first[k], c1 = first[k + 1];
-  const int32_t r = chunks[c0].dst;
-  for (int c = 0; c < bs; c++) {
-    T carry = root[(int64_t)r * bs + c];
-    for (int base = c0; base < c1; base += kBlock * 4) {
-      T x[4];
-      T s = T(0);
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i = base + threadIdx.x * 4 + j;
-        x[j] = i < c1 ? sums[(int64_t)i * bs + c] : T(0);
-        s = Op<OP_SUM, T>::apply(s, x[j]);
-      }
-      T inc = s;
-#pragma unroll
-      for (int d = 1; d < 64; d *= 2) {
-        const T o = shfl_up(inc, d);
-        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
-      }
-      if (lane == 63) wtot[wv] = inc;
-      __syncthreads();
-      T before = carry;
-      for (int w = 0; w < wv; w++) before = Op<OP_SUM, T>::apply(before, wtot[w]);
-      T total = carry;
-      for (int w = 0; w < kBlock / 64; w++) total = Op<OP_SUM, T>::apply(total, wtot[w]);
-      T a = Op<OP_SUM, T>::apply(before, wrap_sub(inc, s));
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i = base + threadIdx.x * 4 + j;
-        if (i < c1) sums[(int64_t)i * bs + c] = a;
-        a = Op<OP_SUM, T>::apply(a, x[j]);
-      }
-      carry = total;
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) root[(int64_t)r * bs + c] = carry;
   }
 }
 
@@ -601,6 +509,7 @@ template <typename T, int OP>
 static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
+  if (OP != OP_REPLACE && h.part) return launch_reduce_part<T, OP>(sf, leaf, root, bs, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
     if (T_)
@@ -650,14 +559,10 @@ static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const int ntiles = (int)h.tiles.size();
-  const int nhot = (int)h.hot_roots.size();
-  const int per = (int)(bs * sizeof(T) + 4);
-  const int nhot_lds = nhot ? std::min(nhot, kHotLdsBytes / per) : 0;
-  const int32_t *ri = nhot ? d.ridx_hot : d.ridx;
-  const unsigned g = (unsigned)std::min(ntiles, kPersistBlocks);
-  const size_t lds = (size_t)nhot_lds * per + 16;
-  hipLaunchKernelGGL((k_reduce_atomic<T, OP>), dim3(g), dim3(kBlock), lds, st, d.segs, d.tiles, ntiles, ri, d.lidx,
-                     d.hot_roots, nhot_lds, leaf, root, bs);
+  const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4);
+  const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
+  hipLaunchKernelGGL((k_reduce_atomic<T, OP>), dim3((unsigned)sh.grid), dim3(kBlock), sh.lds_bytes, st, d.segs,
+                     d.tiles, ntiles, ri, d.lidx, d.hot_roots, sh.nhot_lds, leaf, root, bs);
   return check_launch();
 }
 
@@ -729,16 +634,14 @@ template <typename T>
 static int fop_atomic_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  const unsigned g = (unsigned)h.tiles.size();
-  const int nhot = (int)h.hot_roots.size();
-  if (nhot) {
-    const int per = (int)(bs * sizeof(T) + 4);
-    const int nhot_lds = std::min(nhot, kHotLdsBytes / per);
-    hipLaunchKernelGGL((k_fop_atomic_hot<T>), dim3(g), dim3(kBlock), (size_t)nhot_lds * per + 16, st,
-                       d.segs, d.tiles, d.ridx_hot, d.lidx, d.hot_roots, nhot_lds, root, leaf, upd, bs);
+  const int ntiles = (int)h.tiles.size();
+  if (!h.hot_roots.empty()) {
+    const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4);
+    hipLaunchKernelGGL((k_fop_atomic_hot<T>), dim3((unsigned)sh.grid), dim3(kBlock), sh.lds_bytes, st, d.segs, d.tiles,
+                       ntiles, d.ridx_hot, d.lidx, d.hot_roots, sh.nhot_lds, root, leaf, upd, bs);
   } else {
-    hipLaunchKernelGGL((k_fop_atomic<T>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx, d.lidx, root, leaf,
-                       upd, bs);
+    hipLaunchKernelGGL((k_fop_atomic<T>), dim3((unsigned)ntiles), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx, d.lidx,
+                       root, leaf, upd, bs);
   }
   return check_launch();
 }
@@ -747,6 +650,7 @@ template <typename T>
 static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
+  if (h.part) return launch_fop_part<T>(sf, root, leaf, upd, bs, st);
   for (int c = 0; c < kNumClasses; c++)
     if (!h.cls[c].empty())
       hipLaunchKernelGGL((k_fop_small<T>), dim3(nblocks((int64_t)h.cls[c].size() * bs)), dim3(kBlock), 0, st, d.cls[c],

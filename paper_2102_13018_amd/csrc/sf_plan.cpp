@@ -1,6 +1,6 @@
-// sf_plan.cpp -- host-side analysis of a star forest (PetscSFSetUp,
-// Section 3.1: "sets up internal data structures ... and checks for all
-// possible optimizations") and the upload of the resulting index plan.
+// sf_plan.cpp -- host-side analysis of a star forest (PetscSFSetUp of
+// Section 3.1, which builds the internal structures once and looks for every
+// optimisation it can apply) and the upload of the resulting index plan.
 //
 // What the analysis builds:
 //  * segments: leaves grouped by their rank label, stable in leaf order
@@ -104,6 +104,137 @@ static DevPattern to_dev(const sf_pattern &p) {
   return d;
 }
 
+// The partitioned plan.  Items in sorted order -- a whole root of degree
+// <= kSmallMaxDeg, or one level-0 chunk of a larger root -- are packed
+// greedily into windows of at most kWindow sorted leaves; kBucketWindows
+// consecutive windows form a bucket, bucket b is scheduled on XCD b % kXcd.
+// Pass A writes the p-th processed leaf to scratch slot pp_dst[p]: buckets
+// are contiguous in scratch and, inside a bucket, leaves keep processing
+// order, so each work tile of pass A writes one short contiguous run per
+// bucket.  Pass B reads the g-th sorted leaf from scratch slot pp_src[g],
+// always inside the bucket of its window.
+static int build_partition(HostPlan &hp, const std::vector<int32_t> &perm, const std::vector<int64_t> &proc_leaf,
+                           int64_t L) {
+  const int64_t T = (int64_t)hp.troot.size();
+  // window and bucket sizes: defaults, overridable for tuning sweeps
+  int64_t win_cap = kWindow, bucket_windows = kBucketWindows;
+  if (const char *e = getenv("SF_PP_WINDOW")) win_cap = std::max<int64_t>(kChunk, atoll(e));
+  if (const char *e = getenv("SF_PP_BUCKET")) bucket_windows = std::max<int64_t>(1, atoll(e));
+  // window packing over items in sorted order
+  std::vector<int32_t> bucket_g(L);
+  hp.pp_win.clear();
+  DevWindow cur{0, 0, 0, 0};
+  int64_t cur_n = 0;
+  std::vector<std::pair<int32_t, int32_t>> small_in_win;  // (class, t) of the current window
+  auto close_window = [&]() {
+    std::stable_sort(small_in_win.begin(), small_in_win.end(),
+                     [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) {
+                       return a.first < b.first;
+                     });
+    cur.small0 = (int32_t)hp.pp_small.size();
+    for (auto &x : small_in_win) hp.pp_small.push_back(x.second);
+    cur.small1 = (int32_t)hp.pp_small.size();
+    cur.big1 = (int32_t)hp.pp_big.size();
+    hp.pp_win.push_back(cur);
+    small_in_win.clear();
+    cur = DevWindow{0, 0, (int32_t)hp.pp_big.size(), 0};
+    cur_n = 0;
+  };
+  cur.big0 = 0;
+  int32_t chunk = 0;
+  static const std::vector<DevChunk> none;
+  const std::vector<DevChunk> &lv0 = hp.levels.empty() ? none : hp.levels[0].chunks;
+  for (int64_t t = 0; t < T; t++) {
+    const int32_t g0 = hp.toff[t], n = hp.toff[t + 1] - g0;
+    if (n <= kSmallMaxDeg) {
+      if (cur_n + n > win_cap) close_window();
+      int c = 0;
+      while ((1 << c) < n) c++;
+      small_in_win.push_back({c, (int32_t)t});
+      const int32_t b = (int32_t)(hp.pp_win.size() / bucket_windows);
+      for (int32_t g = g0; g < g0 + n; g++) bucket_g[g] = b;
+      cur_n += n;
+    } else {
+      // this root's level-0 chunks are the next entries of lv0, in order
+      int32_t left = n;
+      while (left > 0) {
+        const DevChunk &ch = lv0[chunk];
+        if (cur_n + ch.n > win_cap) close_window();
+        hp.pp_big.push_back(chunk);
+        const int32_t b = (int32_t)(hp.pp_win.size() / bucket_windows);
+        for (int32_t g = ch.src; g < ch.src + ch.n; g++) bucket_g[g] = b;
+        cur_n += ch.n;
+        left -= ch.n;
+        chunk++;
+      }
+    }
+  }
+  if (cur_n > 0 || hp.pp_win.empty()) close_window();
+  const int64_t W = (int64_t)hp.pp_win.size();
+  const int64_t B = (W + bucket_windows - 1) / bucket_windows;
+  // bucket sizes and bases in scratch
+  std::vector<int64_t> bsize(B, 0), bbase(B + 1, 0);
+  for (int64_t g = 0; g < L; g++) bsize[bucket_g[g]]++;
+  for (int64_t b = 0; b < B; b++) bbase[b + 1] = bbase[b] + bsize[b];
+  // pass A destinations in processing order
+  std::vector<int32_t> pos(L);  // sorted position of leaf i
+  for (int64_t g = 0; g < L; g++) pos[perm[g]] = (int32_t)g;
+  hp.pp_dst.resize(L);
+  std::vector<int64_t> cursor(bbase.begin(), bbase.end() - 1);
+  std::vector<int32_t> proc_of_leaf(L);
+  for (int64_t p = 0; p < L; p++) {
+    const int64_t i = proc_leaf[p];
+    proc_of_leaf[i] = (int32_t)p;
+    hp.pp_dst[p] = (int32_t)cursor[bucket_g[pos[i]]]++;
+  }
+  hp.pp_src.resize(L);
+  for (int64_t g = 0; g < L; g++) hp.pp_src[g] = hp.pp_dst[proc_of_leaf[perm[g]]];
+  // pass A visits each work tile's leaves in increasing scratch slot, so a
+  // tile writes its runs with consecutive lanes; its leaf reads stay inside
+  // the tile's own leaf range
+  hp.pa_dst.resize(L);
+  hp.pa_loc.resize(L);
+  {
+    std::vector<std::pair<int32_t, uint16_t>> tmp;
+    for (const DevTile &tl : hp.tiles) {
+      const int64_t base = hp.dsegs[tl.seg].pbase + tl.t0;
+      const int n = tl.t1 - tl.t0;
+      tmp.resize(n);
+      for (int k = 0; k < n; k++) tmp[k] = {hp.pp_dst[base + k], (uint16_t)k};
+      std::sort(tmp.begin(), tmp.end());
+      for (int k = 0; k < n; k++) {
+        hp.pa_dst[base + k] = tmp[k].first;
+        hp.pa_loc[base + k] = tmp[k].second;
+      }
+    }
+  }
+  // XCD schedule: bucket b on XCD b % kXcd, windows in order
+  std::vector<std::vector<int32_t>> per(kXcd);
+  for (int64_t w = 0; w < W; w++) per[(w / bucket_windows) % kXcd].push_back((int32_t)w);
+  size_t jmax = 0;
+  for (auto &v : per) jmax = std::max(jmax, v.size());
+  hp.pp_jmax = (int32_t)jmax;
+  hp.pp_sched.assign((size_t)kXcd * jmax, -1);
+  for (int x = 0; x < kXcd; x++)
+    for (size_t j = 0; j < per[x].size(); j++) hp.pp_sched[(size_t)x * jmax + j] = per[x][j];
+  // self-check (O(L)): both maps are permutations of the scratch slots and
+  // every sorted leaf of a window reads inside its window's bucket
+  std::vector<uint8_t> seen(L, 0);
+  for (int64_t p = 0; p < L; p++) {
+    const int64_t s = hp.pp_dst[p];
+    if (s < 0 || s >= L || seen[s]) return SF_ERR_ARG;
+    seen[s] = 1;
+  }
+  for (int64_t g = 0; g < L; g++) {
+    const int64_t s = hp.pp_src[g], b = bucket_g[g];
+    if (s < bbase[b] || s >= bbase[b + 1]) return SF_ERR_ARG;
+  }
+  if ((int64_t)hp.pp_big.size() != (int64_t)lv0.size() || (int64_t)hp.pp_big.size() != (int64_t)hp.fo_chunks.size())
+    return SF_ERR_ARG;
+  hp.part = true;
+  return SF_OK;
+}
+
 int analyze(sf_s *sf) {
   const int64_t L = sf->nleaves, R = sf->nroots;
   const bool use_patterns = sf->opts.use_patterns != 0;
@@ -187,16 +318,18 @@ int analyze(sf_s *sf) {
 
   std::vector<int32_t> hot_of(R > 0 ? R : 1, -1);
   if (L >= 65536 && sf->has_dup_roots) {
-    const int64_t hot_min = kPersistBlocks / 2;
     std::vector<int32_t> cand;
     for (int64_t r = 0; r < R; r++)
-      if (deg[r] >= hot_min) cand.push_back((int32_t)r);
+      if (deg[r] >= kHotMinDeg) cand.push_back((int32_t)r);
     std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
     if ((int64_t)cand.size() > kHotMax) cand.resize(kHotMax);
     hp.hot_roots = cand;
+    for (int32_t r : cand) hp.hot_deg.push_back(deg[r]);
     for (size_t h = 0; h < cand.size(); h++) hot_of[cand[h]] = (int32_t)h;
   }
 
+  std::vector<int64_t> proc_leaf;  // leaf index of the p-th processed leaf
+  proc_leaf.reserve(L);
   // ---- index arrays and tiles.  Tiles shrink for small SFs so that the
   // grid still has about four blocks per compute unit.
   int32_t tl = kTileLeaves;
@@ -211,7 +344,9 @@ int analyze(sf_s *sf) {
     d.root = to_dev(ly.root);
     d.leaf = to_dev(ly.leaf);
     d.roff = d.loff = -1;
+    d.pbase = (int32_t)proc_leaf.size();
     auto member = [&](int64_t t) { return ly.members.empty() ? t : ly.members[t]; };
+    for (int64_t t = 0; t < n; t++) proc_leaf.push_back(member(t));
     if (ly.root.kind == SF_PATTERN_GENERIC) {
       d.roff = (int32_t)hp.ridx.size();
       for (int64_t t = 0; t < n; t++) {
@@ -228,7 +363,10 @@ int analyze(sf_s *sf) {
     for (int64_t t0 = 0; t0 < n; t0 += tl)
       hp.tiles.push_back({(int32_t)s, (int32_t)t0, (int32_t)std::min<int64_t>(n, t0 + tl), 0});
   }
-  if (want_hot && hp.ridx_hot.empty()) hp.hot_roots.clear();
+  if (want_hot && hp.ridx_hot.empty()) {
+    hp.hot_roots.clear();
+    hp.hot_deg.clear();
+  }
 
   // ---- root-sorted leaf lists (stable in leaf index)
   std::vector<int32_t> tord(R > 0 ? R : 1, -1);
@@ -241,9 +379,14 @@ int analyze(sf_s *sf) {
   hp.toff.assign(T + 1, 0);
   for (int64_t t = 0; t < T; t++) hp.toff[t + 1] = hp.toff[t] + (int32_t)deg[hp.troot[t]];
   hp.sl.resize(L);
+  std::vector<int32_t> perm(L);  // leaf index of the g-th sorted leaf
   {
     std::vector<int32_t> fill(hp.toff.begin(), hp.toff.end() - 1);
-    for (int64_t i = 0; i < L; i++) hp.sl[fill[tord[sf->iremote[i].index]]++] = (int32_t)slot(i);
+    for (int64_t i = 0; i < L; i++) {
+      const int32_t g = fill[tord[sf->iremote[i].index]]++;
+      hp.sl[g] = (int32_t)slot(i);
+      perm[g] = (int32_t)i;
+    }
   }
   // degree classes: 1, 2, (2,4], (4,8], (8,16], (16,32]; larger -> chunks
   for (int64_t t = 0; t < T; t++) {
@@ -294,6 +437,13 @@ int analyze(sf_s *sf) {
     hp.fo_root_first.push_back((int32_t)hp.fo_chunks.size());
   }
 
+  // ---- partitioned deterministic path
+  const int pmode = sf->opts.partition;  // 0 auto, 1 on, 2 off
+  if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionMin))) {
+    const int rc = build_partition(hp, perm, proc_leaf, L);
+    if (rc) return rc;
+  }
+
   sf->segments = std::move(segs);
   sf->hp = std::move(hp);
   sf->analyzed = true;
@@ -306,6 +456,23 @@ void free_device(sf_s *sf) {
   sf->dp = DevPlan{};
   sf->scratch = nullptr;
   sf->scratch_bytes = 0;
+}
+
+// A block of the persistent atomic kernels sees about L / grid leaves; a
+// root is worth an LDS slot when it has at least half a hit per block
+// (otherwise flushing the slot costs as many atomics as it saves).
+AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes) {
+  int grid = kPersistBlocks;
+  size_t budget = kHotLdsBytes;
+  if (const char *e = getenv("SF_ATOMIC_GRID")) grid = std::max(1, atoi(e));
+  if (const char *e = getenv("SF_HOT_LDS")) budget = (size_t)std::max(0, atoi(e));
+  grid = std::max(1, std::min(grid, ntiles));
+  const HostPlan &h = sf->hp;
+  int n = 0;
+  const int64_t min_deg = std::max<int64_t>(kHotMinDeg, grid / 2);
+  while (n < (int)h.hot_deg.size() && h.hot_deg[n] >= min_deg) n++;
+  n = (int)std::min<size_t>((size_t)n, budget / per_root_bytes);
+  return {grid, n, (size_t)n * per_root_bytes + 16};
 }
 
 int ensure_scratch(sf_s *sf, size_t bytes) {
@@ -352,6 +519,13 @@ int upload(sf_s *sf) {
     add(hp.levels[k].chunks.data(), hp.levels[k].chunks.size() * sizeof(DevChunk), (void **)&dp.levels[k]);
   add(hp.fo_chunks.data(), hp.fo_chunks.size() * sizeof(DevChunk), (void **)&dp.fo_chunks);
   add(hp.fo_root_first.data(), hp.fo_root_first.size() * 4, (void **)&dp.fo_root_first);
+  add(hp.pa_dst.data(), hp.pa_dst.size() * 4, (void **)&dp.pa_dst);
+  add(hp.pa_loc.data(), hp.pa_loc.size() * 2, (void **)&dp.pa_loc);
+  add(hp.pp_src.data(), hp.pp_src.size() * 4, (void **)&dp.pp_src);
+  add(hp.pp_win.data(), hp.pp_win.size() * sizeof(DevWindow), (void **)&dp.pp_win);
+  add(hp.pp_small.data(), hp.pp_small.size() * 4, (void **)&dp.pp_small);
+  add(hp.pp_big.data(), hp.pp_big.size() * 4, (void **)&dp.pp_big);
+  add(hp.pp_sched.data(), hp.pp_sched.size() * 4, (void **)&dp.pp_sched);
 
   size_t total = 0;
   for (auto &p : parts) total += (p.bytes + 255) / 256 * 256;

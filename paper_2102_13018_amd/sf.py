@@ -55,7 +55,7 @@ class SfUnit(ctypes.Structure):
 
 class SfSetupOpts(ctypes.Structure):
     _fields_ = [("reduce_mode", ctypes.c_int32), ("use_patterns", ctypes.c_int32),
-                ("analyze_only", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("analyze_only", ctypes.c_int32), ("partition", ctypes.c_int32)]
 
 
 class SfPattern(ctypes.Structure):
@@ -184,9 +184,10 @@ class StarForest:
         self.nroots = int(nroots)
         self.nleaves = n
 
-    def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False):
+    def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False, partition="auto"):
+        part = {"auto": 0, True: 1, False: 2, "on": 1, "off": 2}[partition]
         o = SfSetupOpts(MODES.get(reduce_mode, reduce_mode), int(bool(use_patterns)),
-                        int(bool(analyze_only)), 0)
+                        int(bool(analyze_only)), part)
         check(lib().sf_setup(self.h, ctypes.byref(o)), "sf_setup")
         return self
 
