@@ -362,7 +362,9 @@ __device__ __forceinline__ int64_t wrap_sub(int64_t a, int64_t b) { return (int6
 }  // namespace sfi
 
 namespace sfi {
-// Launchers of the partitioned deterministic path (sf_partition.hip).
+// Launchers of the partitioned deterministic path (sf_partition.hip), and
+// its unit-size class (0: <= 8 bytes, 1: <= 16 bytes, -1: not staged).
+int stage_class(int64_t unit_bytes);
 template <typename T, int OP>
 int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st);
 template <typename T>

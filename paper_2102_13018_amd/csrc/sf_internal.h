@@ -25,15 +25,13 @@ constexpr int kNumClasses = 6;       // degree classes 1, 2, 4, 8, 16, 32
 constexpr int kHotMax = 8192;        // candidate roots for LDS aggregation on the atomic path
 constexpr int kHotMinDeg = 64;       // smallest degree of such a candidate
 constexpr int kHotLdsBytes = 32768;  // LDS budget for the accumulators, default
-constexpr int kPersistBlocks = 1024; // grid of the persistent atomic kernels, default
-constexpr int kStageBytes = 32768;   // LDS staging of a work tile's leaf units (partitioned path)
-// Partitioned deterministic path: leaves are first scattered into
-// bucket-major scratch (pass A), then reduced window by window (pass B) with
-// the windows of one bucket scheduled on one XCD, so that the gathers of
-// pass B hit that XCD's L2.
-constexpr int kXcd = 8;              // XCDs of an MI355X (work-group i runs on XCD i % 8)
-constexpr int kWindow = 2048;        // sorted leaves per window (one block), default
-constexpr int kBucketWindows = 32;   // windows per bucket, default
+constexpr int kReduceGrid = 512;     // grid of the persistent atomic Reduce (measured best)
+constexpr int kFetchGrid = 1024;     // grid of the persistent atomic FetchAndOp (measured best)
+constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
+// Partitioned deterministic path for large SFs (two fully coalesced passes
+// through a window-major scratch copy of the leaves):
+constexpr int kStageThreads = 1024;      // threads per block of the staged kernels
+constexpr int kStageMaxLds = 131072;     // LDS of one staged block (bytes)
 constexpr int64_t kPartitionMin = 1 << 20;  // automatic partitioning from this many leaves
 
 // --------------------------------------------------------- device structs
@@ -56,9 +54,11 @@ struct DevTile {  // leaves [t0, t1) of segment seg
   int32_t seg, t0, t1, pad;
 };
 
-struct DevWindow {  // items of one window of the partitioned path
+struct DevSWin {  // one window of the partitioned path
+  int32_t base, n;         // its units in scratch: [base, base + n)
   int32_t small0, small1;  // range in the small-root item list
   int32_t big0, big1;      // range in the chunk item list
+  int32_t pad0, pad1;
 };
 
 struct DevChunk {  // one aligned chunk of a root's (sorted) value list
@@ -101,17 +101,19 @@ struct HostPlan {
   // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
   std::vector<DevChunk> fo_chunks;
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
-  // partitioned deterministic path (empty when not used)
+  // partitioned deterministic path: one plan per unit-size class
+  // (class 0: units of <= 8 bytes, class 1: units of 9..16 bytes)
   bool part = false;
-  std::vector<int32_t> pp_dst;    // [L] scratch slot of the p-th processed leaf
-  std::vector<int32_t> pa_dst;    // [L] per work tile, the tile's scratch slots in increasing order
-  std::vector<uint16_t> pa_loc;   // [L] tile-local processing offset of the leaf written to pa_dst[j]
-  std::vector<int32_t> pp_src;    // [L] scratch slot of the g-th sorted leaf (pass B)
-  std::vector<DevWindow> pp_win;
-  std::vector<int32_t> pp_small;  // touched-root ordinals of degree <= kSmallMaxDeg, window-major
-  std::vector<int32_t> pp_big;    // level-0 chunk ordinals, window-major
-  std::vector<int32_t> pp_sched;  // [kXcd * pp_jmax] window ids per XCD, -1 = none
-  int32_t pp_jmax = 0;
+  struct Stage {
+    int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
+    std::vector<DevSWin> win;
+    std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
+    std::vector<uint16_t> lsrc;       // [L] by sorted position: scratch slot minus window base
+    std::vector<int32_t> pa_dst;      // [L] pass-A tile-major, increasing scratch slot in a tile
+    std::vector<uint16_t> pa_loc;     // [L] tile-local processing offset of that leaf
+    std::vector<int32_t> tile_leaf0;  // [ntiles] first slot if the tile's slots are contiguous, else -1
+    std::vector<int32_t> pa_slot;     // [L] slot per processing position (only if some tile is not contiguous)
+  } sp[2];
 };
 
 // Device copy of the plan: one allocation, typed views into it.
@@ -127,10 +129,11 @@ struct DevPlan {
   std::vector<DevChunk *> levels;
   DevChunk *fo_chunks = nullptr;
   int32_t *fo_root_first = nullptr;
-  int32_t *pa_dst = nullptr;
-  uint16_t *pa_loc = nullptr;
-  int32_t *pp_src = nullptr, *pp_small = nullptr, *pp_big = nullptr, *pp_sched = nullptr;
-  DevWindow *pp_win = nullptr;
+  struct Stage {
+    DevSWin *win = nullptr;
+    int32_t *small = nullptr, *big = nullptr, *pa_dst = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
+    uint16_t *lsrc = nullptr, *pa_loc = nullptr;
+  } sp[2];
 };
 
 struct Pending {
@@ -187,5 +190,5 @@ struct AtomicShape {
   int nhot_lds;
   size_t lds_bytes;
 };
-AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes);
+AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes, int grid);
 }  // namespace sfi

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast_move(const DevSegment *__restr
   const DevSegment sg = segs[tl.seg];
   const int w = W > 0 ? W : wrt;
   const int items = (tl.t1 - tl.t0) * w;
-  constexpr int U = 4;
+  constexpr int U = 8;  // loads in flight per thread
   for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * U) {
     Word v[U];
     int64_t dst[U];
@@ -509,7 +509,8 @@ template <typename T, int OP>
 static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (OP != OP_REPLACE && h.part) return launch_reduce_part<T, OP>(sf, leaf, root, bs, st);
+  if (OP != OP_REPLACE && h.part && stage_class((int64_t)sizeof(T) * bs) >= 0)
+    return launch_reduce_part<T, OP>(sf, leaf, root, bs, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
     if (T_)
@@ -559,7 +560,7 @@ static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const int ntiles = (int)h.tiles.size();
-  const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4);
+  const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kReduceGrid);
   const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
   hipLaunchKernelGGL((k_reduce_atomic<T, OP>), dim3((unsigned)sh.grid), dim3(kBlock), sh.lds_bytes, st, d.segs,
                      d.tiles, ntiles, ri, d.lidx, d.hot_roots, sh.nhot_lds, leaf, root, bs);
@@ -636,7 +637,7 @@ static int fop_atomic_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStr
   const HostPlan &h = sf->hp;
   const int ntiles = (int)h.tiles.size();
   if (!h.hot_roots.empty()) {
-    const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4);
+    const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kFetchGrid);
     hipLaunchKernelGGL((k_fop_atomic_hot<T>), dim3((unsigned)sh.grid), dim3(kBlock), sh.lds_bytes, st, d.segs, d.tiles,
                        ntiles, d.ridx_hot, d.lidx, d.hot_roots, sh.nhot_lds, root, leaf, upd, bs);
   } else {
@@ -650,7 +651,7 @@ template <typename T>
 static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (h.part) return launch_fop_part<T>(sf, root, leaf, upd, bs, st);
+  if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, st);
   for (int c = 0; c < kNumClasses; c++)
     if (!h.cls[c].empty())
       hipLaunchKernelGGL((k_fop_small<T>), dim3(nblocks((int64_t)h.cls[c].size() * bs)), dim3(kBlock), 0, st, d.cls[c],

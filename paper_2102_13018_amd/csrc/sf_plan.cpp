@@ -104,135 +104,144 @@ static DevPattern to_dev(const sf_pattern &p) {
   return d;
 }
 
-// The partitioned plan.  Items in sorted order -- a whole root of degree
-// <= kSmallMaxDeg, or one level-0 chunk of a larger root -- are packed
-// greedily into windows of at most kWindow sorted leaves; kBucketWindows
-// consecutive windows form a bucket, bucket b is scheduled on XCD b % kXcd.
-// Pass A writes the p-th processed leaf to scratch slot pp_dst[p]: buckets
-// are contiguous in scratch and, inside a bucket, leaves keep processing
-// order, so each work tile of pass A writes one short contiguous run per
-// bucket.  Pass B reads the g-th sorted leaf from scratch slot pp_src[g],
-// always inside the bucket of its window.
-static int build_partition(HostPlan &hp, const std::vector<int32_t> &perm, const std::vector<int64_t> &proc_leaf,
-                           int64_t L) {
+// The partitioned plan of one unit-size class.  Items in sorted order -- a
+// whole root of degree <= kSmallMaxDeg, or one level-0 chunk of a larger
+// root -- are packed greedily into windows of at most `cap` sorted leaves.
+// Scratch is window-major and, inside a window, in processing order, so:
+//  * pass A, which moves the leaves of `ta` consecutive processing positions
+//    (one pass-A tile) into scratch, writes one contiguous run per window,
+//    in increasing slot order (pa_dst / pa_loc);
+//  * pass B loads one window's contiguous scratch range into LDS and reads
+//    the g-th sorted leaf at LDS offset lsrc[g].
+static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int32_t> &perm,
+                       const std::vector<int64_t> &proc_leaf, const std::vector<int32_t> &proc_slot, int64_t L,
+                       int32_t ta, int32_t cap) {
   const int64_t T = (int64_t)hp.troot.size();
-  // window and bucket sizes: defaults, overridable for tuning sweeps
-  int64_t win_cap = kWindow, bucket_windows = kBucketWindows;
-  if (const char *e = getenv("SF_PP_WINDOW")) win_cap = std::max<int64_t>(kChunk, atoll(e));
-  if (const char *e = getenv("SF_PP_BUCKET")) bucket_windows = std::max<int64_t>(1, atoll(e));
-  // window packing over items in sorted order
-  std::vector<int32_t> bucket_g(L);
-  hp.pp_win.clear();
-  DevWindow cur{0, 0, 0, 0};
+  sp = HostPlan::Stage();
+  sp.ta = ta;
+  sp.cap = cap;
+  std::vector<int32_t> win_g(L);  // window of the g-th sorted leaf
+  DevSWin cur{};
   int64_t cur_n = 0;
-  std::vector<std::pair<int32_t, int32_t>> small_in_win;  // (class, t) of the current window
+  std::vector<std::pair<int32_t, int32_t>> small_in_win;  // (class, t)
   auto close_window = [&]() {
     std::stable_sort(small_in_win.begin(), small_in_win.end(),
-                     [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) {
-                       return a.first < b.first;
+                     [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+                       return x.first < y.first;
                      });
-    cur.small0 = (int32_t)hp.pp_small.size();
-    for (auto &x : small_in_win) hp.pp_small.push_back(x.second);
-    cur.small1 = (int32_t)hp.pp_small.size();
-    cur.big1 = (int32_t)hp.pp_big.size();
-    hp.pp_win.push_back(cur);
+    cur.small0 = (int32_t)sp.small.size();
+    for (auto &x : small_in_win) sp.small.push_back(x.second);
+    cur.small1 = (int32_t)sp.small.size();
+    cur.big1 = (int32_t)sp.big.size();
+    cur.n = (int32_t)cur_n;
+    sp.win.push_back(cur);
     small_in_win.clear();
-    cur = DevWindow{0, 0, (int32_t)hp.pp_big.size(), 0};
+    cur = DevSWin{};
+    cur.big0 = (int32_t)sp.big.size();
     cur_n = 0;
   };
-  cur.big0 = 0;
-  int32_t chunk = 0;
   static const std::vector<DevChunk> none;
   const std::vector<DevChunk> &lv0 = hp.levels.empty() ? none : hp.levels[0].chunks;
+  int32_t chunk = 0;
   for (int64_t t = 0; t < T; t++) {
     const int32_t g0 = hp.toff[t], n = hp.toff[t + 1] - g0;
     if (n <= kSmallMaxDeg) {
-      if (cur_n + n > win_cap) close_window();
+      if (cur_n + n > cap) close_window();
       int c = 0;
       while ((1 << c) < n) c++;
       small_in_win.push_back({c, (int32_t)t});
-      const int32_t b = (int32_t)(hp.pp_win.size() / bucket_windows);
-      for (int32_t g = g0; g < g0 + n; g++) bucket_g[g] = b;
+      for (int32_t g = g0; g < g0 + n; g++) win_g[g] = (int32_t)sp.win.size();
       cur_n += n;
     } else {
-      // this root's level-0 chunks are the next entries of lv0, in order
-      int32_t left = n;
+      int32_t left = n;  // this root's level-0 chunks are the next entries of lv0
       while (left > 0) {
         const DevChunk &ch = lv0[chunk];
-        if (cur_n + ch.n > win_cap) close_window();
-        hp.pp_big.push_back(chunk);
-        const int32_t b = (int32_t)(hp.pp_win.size() / bucket_windows);
-        for (int32_t g = ch.src; g < ch.src + ch.n; g++) bucket_g[g] = b;
+        if (cur_n + ch.n > cap) close_window();
+        sp.big.push_back(chunk);
+        for (int32_t g = ch.src; g < ch.src + ch.n; g++) win_g[g] = (int32_t)sp.win.size();
         cur_n += ch.n;
         left -= ch.n;
         chunk++;
       }
     }
   }
-  if (cur_n > 0 || hp.pp_win.empty()) close_window();
-  const int64_t W = (int64_t)hp.pp_win.size();
-  const int64_t B = (W + bucket_windows - 1) / bucket_windows;
-  // bucket sizes and bases in scratch
-  std::vector<int64_t> bsize(B, 0), bbase(B + 1, 0);
-  for (int64_t g = 0; g < L; g++) bsize[bucket_g[g]]++;
-  for (int64_t b = 0; b < B; b++) bbase[b + 1] = bbase[b] + bsize[b];
-  // pass A destinations in processing order
-  std::vector<int32_t> pos(L);  // sorted position of leaf i
+  if (cur_n > 0 || sp.win.empty()) close_window();
+  const int64_t W = (int64_t)sp.win.size();
+  int64_t base = 0;
+  for (int64_t w = 0; w < W; w++) {
+    sp.win[w].base = (int32_t)base;
+    base += sp.win[w].n;
+  }
+  if (base != L || chunk != (int32_t)lv0.size() || lv0.size() != hp.fo_chunks.size()) return SF_ERR_ARG;
+  // scratch slot of every processed leaf: window base + rank in processing order
+  std::vector<int32_t> pos(L);
   for (int64_t g = 0; g < L; g++) pos[perm[g]] = (int32_t)g;
-  hp.pp_dst.resize(L);
-  std::vector<int64_t> cursor(bbase.begin(), bbase.end() - 1);
+  std::vector<int32_t> dst(L), cursor(W);
+  for (int64_t w = 0; w < W; w++) cursor[w] = sp.win[w].base;
   std::vector<int32_t> proc_of_leaf(L);
   for (int64_t p = 0; p < L; p++) {
     const int64_t i = proc_leaf[p];
     proc_of_leaf[i] = (int32_t)p;
-    hp.pp_dst[p] = (int32_t)cursor[bucket_g[pos[i]]]++;
+    dst[p] = cursor[win_g[pos[i]]]++;
   }
-  hp.pp_src.resize(L);
-  for (int64_t g = 0; g < L; g++) hp.pp_src[g] = hp.pp_dst[proc_of_leaf[perm[g]]];
-  // pass A visits each work tile's leaves in increasing scratch slot, so a
-  // tile writes its runs with consecutive lanes; its leaf reads stay inside
-  // the tile's own leaf range
-  hp.pa_dst.resize(L);
-  hp.pa_loc.resize(L);
-  {
-    std::vector<std::pair<int32_t, uint16_t>> tmp;
-    for (const DevTile &tl : hp.tiles) {
-      const int64_t base = hp.dsegs[tl.seg].pbase + tl.t0;
-      const int n = tl.t1 - tl.t0;
-      tmp.resize(n);
-      for (int k = 0; k < n; k++) tmp[k] = {hp.pp_dst[base + k], (uint16_t)k};
-      std::sort(tmp.begin(), tmp.end());
-      for (int k = 0; k < n; k++) {
-        hp.pa_dst[base + k] = tmp[k].first;
-        hp.pa_loc[base + k] = tmp[k].second;
-      }
+  sp.lsrc.resize(L);
+  for (int64_t g = 0; g < L; g++) {
+    const int64_t off = dst[proc_of_leaf[perm[g]]] - (int64_t)sp.win[win_g[g]].base;
+    if (off < 0 || off >= sp.win[win_g[g]].n || off > 65535) return SF_ERR_ARG;
+    sp.lsrc[g] = (uint16_t)off;
+  }
+  // pass-A tiles: increasing scratch slot inside each tile
+  const int64_t ntiles = (L + ta - 1) / ta;
+  sp.pa_dst.resize(L);
+  sp.pa_loc.resize(L);
+  sp.tile_leaf0.assign(ntiles, -1);
+  bool gather = false;
+  // inside a window, slots increase with processing position, so ordering a
+  // tile by slot is a stable counting sort of its leaves by window
+  std::vector<int32_t> wofp(L);
+  for (int64_t p = 0; p < L; p++) wofp[p] = win_g[pos[proc_leaf[p]]];
+  std::vector<int32_t> cnt(W + 1, 0);
+  for (int64_t k = 0; k < ntiles; k++) {
+    const int64_t p0 = k * ta, n = std::min<int64_t>(ta, L - p0);
+    int32_t wlo = INT32_MAX, whi = -1;
+    bool contiguous = true;
+    for (int64_t q = 0; q < n; q++) {
+      wlo = std::min(wlo, wofp[p0 + q]);
+      whi = std::max(whi, wofp[p0 + q]);
+      if (proc_slot[p0 + q] != proc_slot[p0] + q) contiguous = false;
     }
+    std::fill(cnt.begin() + wlo, cnt.begin() + whi + 2, 0);
+    for (int64_t q = 0; q < n; q++) cnt[wofp[p0 + q] + 1]++;
+    for (int32_t w = wlo; w <= whi; w++) cnt[w + 1] += cnt[w];
+    for (int64_t q = 0; q < n; q++) {
+      const int32_t at = cnt[wofp[p0 + q]]++;
+      sp.pa_dst[p0 + at] = dst[p0 + q];
+      sp.pa_loc[p0 + at] = (uint16_t)q;
+    }
+    for (int64_t q = 1; q < n; q++)
+      if (sp.pa_dst[p0 + q] <= sp.pa_dst[p0 + q - 1]) return SF_ERR_ARG;
+    if (contiguous) sp.tile_leaf0[k] = proc_slot[p0];
+    else gather = true;
   }
-  // XCD schedule: bucket b on XCD b % kXcd, windows in order
-  std::vector<std::vector<int32_t>> per(kXcd);
-  for (int64_t w = 0; w < W; w++) per[(w / bucket_windows) % kXcd].push_back((int32_t)w);
-  size_t jmax = 0;
-  for (auto &v : per) jmax = std::max(jmax, v.size());
-  hp.pp_jmax = (int32_t)jmax;
-  hp.pp_sched.assign((size_t)kXcd * jmax, -1);
-  for (int x = 0; x < kXcd; x++)
-    for (size_t j = 0; j < per[x].size(); j++) hp.pp_sched[(size_t)x * jmax + j] = per[x][j];
-  // self-check (O(L)): both maps are permutations of the scratch slots and
-  // every sorted leaf of a window reads inside its window's bucket
+  if (gather) sp.pa_slot = proc_slot;
+  // self-check: dst is a permutation of the scratch slots
   std::vector<uint8_t> seen(L, 0);
   for (int64_t p = 0; p < L; p++) {
-    const int64_t s = hp.pp_dst[p];
-    if (s < 0 || s >= L || seen[s]) return SF_ERR_ARG;
-    seen[s] = 1;
+    if (dst[p] < 0 || dst[p] >= L || seen[dst[p]]) return SF_ERR_ARG;
+    seen[dst[p]] = 1;
   }
-  for (int64_t g = 0; g < L; g++) {
-    const int64_t s = hp.pp_src[g], b = bucket_g[g];
-    if (s < bbase[b] || s >= bbase[b + 1]) return SF_ERR_ARG;
-  }
-  if ((int64_t)hp.pp_big.size() != (int64_t)lv0.size() || (int64_t)hp.pp_big.size() != (int64_t)hp.fo_chunks.size())
-    return SF_ERR_ARG;
-  hp.part = true;
   return SF_OK;
+}
+
+// Window and tile sizes per unit-size class (overridable for tuning sweeps).
+static void stage_sizes(int cls, int32_t *ta, int32_t *cap) {
+  const int64_t ub = cls == 0 ? 8 : 16;
+  *ta = (int32_t)(kStageMaxLds / ub);
+  *cap = cls == 0 ? 8192 : 8192;
+  if (const char *e = getenv(cls == 0 ? "SF_SP0_CAP" : "SF_SP1_CAP")) *cap = atoi(e);
+  if (const char *e = getenv(cls == 0 ? "SF_SP0_TA" : "SF_SP1_TA")) *ta = atoi(e);
+  *cap = std::max<int32_t>(kChunk, std::min<int32_t>(*cap, (int32_t)(kStageMaxLds / ub)));
+  *ta = std::max<int32_t>(256, std::min<int32_t>(*ta, (int32_t)(kStageMaxLds / ub)));
 }
 
 int analyze(sf_s *sf) {
@@ -440,8 +449,15 @@ int analyze(sf_s *sf) {
   // ---- partitioned deterministic path
   const int pmode = sf->opts.partition;  // 0 auto, 1 on, 2 off
   if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionMin))) {
-    const int rc = build_partition(hp, perm, proc_leaf, L);
-    if (rc) return rc;
+    std::vector<int32_t> proc_slot(L);
+    for (int64_t p = 0; p < L; p++) proc_slot[p] = (int32_t)slot(proc_leaf[p]);
+    for (int cls = 0; cls < 2; cls++) {
+      int32_t ta, cap;
+      stage_sizes(cls, &ta, &cap);
+      const int rc = build_stage(hp, hp.sp[cls], perm, proc_leaf, proc_slot, L, ta, cap);
+      if (rc) return rc;
+    }
+    hp.part = true;
   }
 
   sf->segments = std::move(segs);
@@ -461,8 +477,7 @@ void free_device(sf_s *sf) {
 // A block of the persistent atomic kernels sees about L / grid leaves; a
 // root is worth an LDS slot when it has at least half a hit per block
 // (otherwise flushing the slot costs as many atomics as it saves).
-AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes) {
-  int grid = kPersistBlocks;
+AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes, int grid) {
   size_t budget = kHotLdsBytes;
   if (const char *e = getenv("SF_ATOMIC_GRID")) grid = std::max(1, atoi(e));
   if (const char *e = getenv("SF_HOT_LDS")) budget = (size_t)std::max(0, atoi(e));
@@ -519,13 +534,18 @@ int upload(sf_s *sf) {
     add(hp.levels[k].chunks.data(), hp.levels[k].chunks.size() * sizeof(DevChunk), (void **)&dp.levels[k]);
   add(hp.fo_chunks.data(), hp.fo_chunks.size() * sizeof(DevChunk), (void **)&dp.fo_chunks);
   add(hp.fo_root_first.data(), hp.fo_root_first.size() * 4, (void **)&dp.fo_root_first);
-  add(hp.pa_dst.data(), hp.pa_dst.size() * 4, (void **)&dp.pa_dst);
-  add(hp.pa_loc.data(), hp.pa_loc.size() * 2, (void **)&dp.pa_loc);
-  add(hp.pp_src.data(), hp.pp_src.size() * 4, (void **)&dp.pp_src);
-  add(hp.pp_win.data(), hp.pp_win.size() * sizeof(DevWindow), (void **)&dp.pp_win);
-  add(hp.pp_small.data(), hp.pp_small.size() * 4, (void **)&dp.pp_small);
-  add(hp.pp_big.data(), hp.pp_big.size() * 4, (void **)&dp.pp_big);
-  add(hp.pp_sched.data(), hp.pp_sched.size() * 4, (void **)&dp.pp_sched);
+  for (int c = 0; c < 2; c++) {
+    HostPlan::Stage &sp = hp.sp[c];
+    DevPlan::Stage &ds = dp.sp[c];
+    add(sp.win.data(), sp.win.size() * sizeof(DevSWin), (void **)&ds.win);
+    add(sp.small.data(), sp.small.size() * 4, (void **)&ds.small);
+    add(sp.big.data(), sp.big.size() * 4, (void **)&ds.big);
+    add(sp.lsrc.data(), sp.lsrc.size() * 2, (void **)&ds.lsrc);
+    add(sp.pa_dst.data(), sp.pa_dst.size() * 4, (void **)&ds.pa_dst);
+    add(sp.pa_loc.data(), sp.pa_loc.size() * 2, (void **)&ds.pa_loc);
+    add(sp.tile_leaf0.data(), sp.tile_leaf0.size() * 4, (void **)&ds.tile_leaf0);
+    add(sp.pa_slot.data(), sp.pa_slot.size() * 4, (void **)&ds.pa_slot);
+  }
 
   size_t total = 0;
   for (auto &p : parts) total += (p.bytes + 255) / 256 * 256;

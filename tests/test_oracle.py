@@ -409,3 +409,23 @@ def test_oracle_rejects_bad_graphs(orc):
         orc.bcast(3, [0, -1], None, np.zeros(3), np.zeros(2), "replace")
     with pytest.raises(ValueError):
         orc.reduce(3, [0, 1], None, np.zeros(2), np.zeros(3), "maxloc")  # MAXLOC needs pair units
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_fetch_and_op_float_matches_integer_chain(orc, dtype):
+    """With small integer-valued floats every partial sum is exact, so the FP
+    FetchAndOp must give exactly the integer version's numbers (leaf order,
+    Section 3.2); MAX/MIN fetch the running extreme."""
+    g = inputs.single_sf(seed=5, nroots=300, nleaves=2000, leafspace=2500)
+    rng = np.random.default_rng(21)
+    ri = rng.integers(0, 100, g.nroots).astype(np.int64)
+    li = rng.integers(0, 100, g.leafspace).astype(np.int64)
+    wr, wu = orc.fetch_and_op(g.nroots, g.iroot, g.ilocal, ri, li, np.zeros(g.leafspace, np.int64))
+    r, u = orc.fetch_and_op(g.nroots, g.iroot, g.ilocal, ri.astype(dtype), li.astype(dtype),
+                            np.zeros(g.leafspace, dtype))
+    assert np.array_equal(r, wr.astype(dtype)) and np.array_equal(u, wu.astype(dtype))
+    r, u = orc.fetch_and_op(g.nroots, g.iroot, g.ilocal, ri.astype(dtype), li.astype(dtype),
+                            np.zeros(g.leafspace, dtype), "max")
+    want = ri.astype(dtype).copy()
+    np.maximum.at(want, g.iroot, li[g.ilocal].astype(dtype))
+    assert np.array_equal(r, want)
