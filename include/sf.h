@@ -24,6 +24,8 @@
  *  - stream is a hipStream_t (NULL = the null stream).  Begin enqueues the
  *    kernels; End is stream-ordered and never blocks the host: results are
  *    visible to later work on the same stream (or after synchronising it).
+ *    With the environment variable SF_DEBUG=1, *_begin queries each data
+ *    pointer and returns SF_ERR_ARG for memory that is not device memory.
  *  - Device indices are 32-bit: nroots and the leaf space must be < 2^31.
  *  - An SF and its scratch memory may be used by one stream at a time.
  */

@@ -3,6 +3,7 @@
 // (PetscSFSetUp), begin/end pairs of Bcast / Reduce / FetchAndOp with their
 // argument bookkeeping (Section 3.2), inspection and error strings.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -123,6 +124,20 @@ static int begin_common(sf_t sf, int kind, sf_unit unit, int32_t op, const void 
   }
   for (const Pending &p : sf->pending)
     if (p.kind == kind && p.a == a && p.b == b && p.c == c) return SF_ERR_BUSY;
+  // SF_DEBUG=1: reject host memory (one pointer query per buffer; the
+  // paper's Section 5.3 notes such a query costs about 0.3 us, so it is off
+  // by default and the caller is trusted to pass device pointers)
+  static const bool debug = getenv("SF_DEBUG") && atoi(getenv("SF_DEBUG")) > 0;
+  if (debug && sf->nleaves > 0) {
+    for (const void *ptr : {a, b, c}) {
+      if (!ptr) continue;
+      hipPointerAttribute_t at;
+      if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return SF_ERR_ARG;
+      }
+    }
+  }
   return SF_OK;
 }
 

@@ -85,6 +85,7 @@ struct HostPlan {
   std::vector<DevSegment> dsegs;
   std::vector<DevTile> tiles;
   int32_t tile_leaves = kTileLeaves;  // leaves per tile of this SF
+  bool all_contig = false;            // every segment contiguous on both sides (few segments)
   std::vector<int32_t> ridx;      // root index per processed leaf (generic root sides)
   std::vector<int32_t> ridx_hot;  // same, hot roots encoded as -(h+1)
   std::vector<int32_t> lidx;      // leaf slot per processed leaf (generic leaf sides)

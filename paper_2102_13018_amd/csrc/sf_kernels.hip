@@ -464,9 +464,26 @@ static int bcast_op_t(sf_s *sf, int bs, int op, const void *root, void *leaf, hi
   return SF_OK;
 }
 
+// Contiguous roots and contiguous leaves in every segment (Section 5.2: no
+// pack needed): a REPLACE is one device-to-device copy per segment.
+// dir 0: root -> leaf (Bcast), dir 1: leaf -> root (Reduce without
+// duplicate roots).
+static int copy_segments(sf_s *sf, int64_t ub, const void *root, void *leafv, int dir, hipStream_t st) {
+  for (const DevSegment &d : sf->hp.dsegs) {
+    char *r = (char *)root + (int64_t)d.root.start * ub;
+    char *l = (char *)leafv + (int64_t)d.leaf.start * ub;
+    hipError_t e = dir == 0 ? hipMemcpyAsync(l, r, (size_t)d.n * ub, hipMemcpyDeviceToDevice, st)
+                            : hipMemcpyAsync(r, l, (size_t)d.n * ub, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return set_hip_error(e);
+  }
+  return SF_OK;
+}
+
 int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, hipStream_t st) {
   if (sf->hp.tiles.empty()) return SF_OK;
   const int es = elem_size(unit.dtype);
+  if (op == SF_REPLACE && unit.dtype != SF_F64_I32 && sf->hp.all_contig)
+    return copy_segments(sf, (int64_t)es * unit.bs, root, leaf, 0, st);
   if (op == SF_REPLACE && unit.dtype != SF_F64_I32) {
     const int64_t ub = (int64_t)es * unit.bs;
     const uintptr_t a = (uintptr_t)root | (uintptr_t)leaf;
@@ -608,6 +625,8 @@ static int reduce_t(sf_s *sf, int op, int mode, const void *leafv, void *rootv, 
 
 int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, hipStream_t st) {
   if (sf->nleaves == 0) return SF_OK;
+  if (op == SF_REPLACE && unit.dtype != SF_F64_I32 && sf->hp.all_contig && !sf->has_dup_roots)
+    return copy_segments(sf, (int64_t)elem_size(unit.dtype) * unit.bs, root, (void *)leaf, 1, st);
   const int mode = sf->reduce_mode;
   switch (unit.dtype) {
     case SF_F64: return reduce_t<double>(sf, op, mode, leaf, root, unit.bs, st);

@@ -372,6 +372,10 @@ int analyze(sf_s *sf) {
     for (int64_t t0 = 0; t0 < n; t0 += tl)
       hp.tiles.push_back({(int32_t)s, (int32_t)t0, (int32_t)std::min<int64_t>(n, t0 + tl), 0});
   }
+  // contiguous on both sides in every segment: a REPLACE is a plain copy
+  hp.all_contig = !hp.dsegs.empty() && hp.dsegs.size() <= 64;
+  for (const DevSegment &d : hp.dsegs)
+    if (d.root.kind != SF_PATTERN_CONTIGUOUS || d.leaf.kind != SF_PATTERN_CONTIGUOUS) hp.all_contig = false;
   if (want_hot && hp.ridx_hot.empty()) {
     hp.hot_roots.clear();
     hp.hot_deg.clear();

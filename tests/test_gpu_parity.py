@@ -322,3 +322,24 @@ def test_determinism_across_runs(zipf):
     a = gpu_reduce(sf, leaf, root)
     b = gpu_reduce(sf, leaf, root)
     assert same_bits(a, b)
+
+
+def test_contiguous_segments_copy_and_ping_pong():
+    """Every segment contiguous on both sides (Section 5.2's no-pack case):
+    Bcast REPLACE is a device copy per segment; the ping-pong of Table 1's
+    test (Bcast then Reduce REPLACE on a one-to-one SF) restores the roots."""
+    n = 1000
+    # two segments: leaves 0..599 <- roots 400..999, leaves 600..999 <- roots 0..399
+    iroot = np.concatenate([np.arange(400, 1000), np.arange(0, 400)])
+    ranks = np.concatenate([np.zeros(600, np.int64), np.ones(400, np.int64)])
+    g = inputs.Graph(n, iroot, None, ranks, n)
+    rng = np.random.default_rng(900)
+    for dtype, bs in [(np.float64, 1), (np.float32, 3), (np.int32, 1)]:
+        root = inputs.unit_data(rng, n, bs, dtype)
+        leaf = inputs.unit_data(rng, n, bs, dtype)
+        sf = make_sf(g)
+        assert sf.segment(0)["root"]["kind"] == S.SF_PATTERN_CONTIGUOUS
+        got = gpu_bcast(sf, root, leaf)
+        assert_same(got, oracle.bcast(n, iroot, None, root, leaf), "contiguous bcast")
+        back = gpu_reduce(sf, got, np.zeros_like(root), "replace")
+        assert_same(back, root, "ping-pong round trip")
