@@ -370,3 +370,35 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st)
 template <typename T>
 int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st);
 }  // namespace sfi
+
+namespace sfi {
+// NV consecutive elements of one unit, moved with one vector access.
+template <typename T, int NV>
+struct alignas(sizeof(T) * NV) Vec {
+  T x[NV];
+};
+template <int OP, typename T, int NV>
+__device__ __forceinline__ Vec<T, NV> vop(const Vec<T, NV> &a, const Vec<T, NV> &b) {
+  Vec<T, NV> r;
+#pragma unroll
+  for (int i = 0; i < NV; i++) r.x[i] = Op<OP, T>::apply(a.x[i], b.x[i]);
+  return r;
+}
+template <typename T, int NV>
+__device__ __forceinline__ Vec<T, NV> vld(const T *p) {
+  if constexpr (NV == 1) {
+    Vec<T, 1> r;
+    r.x[0] = ld(p);
+    return r;
+  } else {
+    return *reinterpret_cast<const Vec<T, NV> *>(p);
+  }
+}
+template <typename T, int NV>
+__device__ __forceinline__ void vst(T *p, const Vec<T, NV> &v) {
+  if constexpr (NV == 1)
+    st(p, v.x[0]);
+  else
+    *reinterpret_cast<Vec<T, NV> *>(p) = v;
+}
+}  // namespace sfi

@@ -97,6 +97,7 @@ struct HostPlan {
   std::vector<int32_t> sl;        // leaf slot of the g-th leaf in (root, leaf) order
   std::vector<int32_t> cls[kNumClasses];  // touched-root ordinals per degree class
   std::vector<int32_t> large;     // touched-root ordinals with degree > kSmallMaxDeg
+  std::vector<int32_t> small_all; // the degree classes concatenated, class by class
   std::vector<ChunkLevel> levels; // chunk levels of the large roots
   int64_t scratch_len = 0;        // max sequence length written by a chunk level
   // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
@@ -127,6 +128,7 @@ struct DevPlan {
   int32_t *troot = nullptr, *toff = nullptr, *sl = nullptr;
   int32_t *cls[kNumClasses] = {};
   int32_t *large = nullptr;
+  int32_t *small_all = nullptr;
   std::vector<DevChunk *> levels;
   DevChunk *fo_chunks = nullptr;
   int32_t *fo_root_first = nullptr;

@@ -210,33 +210,54 @@ __global__ __launch_bounds__(kBlock) void k_maxloc_stream(const DevSegment *__re
 }
 
 // ============================================== Reduce: deterministic kinds
-// Roots of degree n <= D (one class): one thread per (root, element); the
-// leaves are loaded in leaf order into registers and combined bottom-up
-// (pairs (p, p+d) for p a multiple of 2d and p + d < n): the canonical
-// pairwise tree.  The root is combined last, as the left operand.
-template <typename T, int OP, int D>
-__global__ __launch_bounds__(kBlock) void k_det_small(const int32_t *__restrict__ cls, int count,
-                                                      const int32_t *__restrict__ troot,
-                                                      const int32_t *__restrict__ toff,
-                                                      const int32_t *__restrict__ sl, const T *__restrict__ leaf,
-                                                      T *__restrict__ root, int bs) {
-  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (q >= (int64_t)count * bs) return;
-  const int k = (int)(q / bs), c = (int)(q % bs);
-  const int t = cls[k];
-  const int g0 = toff[t];
-  const int n = toff[t + 1] - g0;
-  T x[D];
+// All roots of degree <= kSmallMaxDeg in one launch (the classes
+// concatenated, so a wavefront mostly sees one class): one thread per (root,
+// group of NV consecutive elements), the leaves loaded in leaf order into
+// registers with vector loads and combined bottom-up -- the canonical
+// pairwise tree, element by element.  The root is combined last.
+template <typename T, int OP, int NV, int D>
+__device__ __forceinline__ Vec<T, NV> small_tree_v(const int32_t *__restrict__ sl, const T *__restrict__ leaf, int g0,
+                                                   int n, int bs, int c) {
+  Vec<T, NV> x[D];
 #pragma unroll
   for (int p = 0; p < D; p++)
-    if (p < n) x[p] = ld(leaf + (int64_t)sl[g0 + p] * bs + c);
+    if (p < n) x[p] = vld<T, NV>(leaf + (int64_t)sl[g0 + p] * bs + c);
 #pragma unroll
   for (int d = 1; d < D; d *= 2)
 #pragma unroll
     for (int p = 0; p + d < D; p += 2 * d)
-      if (p + d < n) x[p] = Op<OP, T>::apply(x[p], x[p + d]);
+      if (p + d < n) x[p] = vop<OP, T, NV>(x[p], x[p + d]);
+  return x[0];
+}
+
+template <typename T, int OP, int NV>
+__global__ __launch_bounds__(kBlock) void k_det_small_all(const int32_t *__restrict__ list, int count,
+                                                          const int32_t *__restrict__ troot,
+                                                          const int32_t *__restrict__ toff,
+                                                          const int32_t *__restrict__ sl, const T *__restrict__ leaf,
+                                                          T *__restrict__ root, int bs) {
+  const int nv = bs / NV;
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= (int64_t)count * nv) return;
+  const int k = (int)(q / nv), c = (int)(q - (int64_t)k * nv) * NV;
+  const int t = list[k];
+  const int g0 = toff[t];
+  const int n = toff[t + 1] - g0;
+  Vec<T, NV> v;
+  if (n <= 1)
+    v = small_tree_v<T, OP, NV, 1>(sl, leaf, g0, n, bs, c);
+  else if (n <= 2)
+    v = small_tree_v<T, OP, NV, 2>(sl, leaf, g0, n, bs, c);
+  else if (n <= 4)
+    v = small_tree_v<T, OP, NV, 4>(sl, leaf, g0, n, bs, c);
+  else if (n <= 8)
+    v = small_tree_v<T, OP, NV, 8>(sl, leaf, g0, n, bs, c);
+  else if (n <= 16)
+    v = small_tree_v<T, OP, NV, 16>(sl, leaf, g0, n, bs, c);
+  else
+    v = small_tree_v<T, OP, NV, 32>(sl, leaf, g0, n, bs, c);
   T *rp = root + (int64_t)troot[t] * bs + c;
-  st(rp, Op<OP, T>::apply(ld(rp), x[0]));
+  vst<T, NV>(rp, vop<OP, T, NV>(vld<T, NV>(rp), v));
 }
 
 // Reduce REPLACE with duplicate roots: the last leaf in leaf order wins.
@@ -292,23 +313,47 @@ __global__ __launch_bounds__(kBlock) void k_fop_atomic_hot(const DevSegment *__r
   for (int k = threadIdx.x; k < nhot_lds * bs; k += kBlock) acc[k] = T(0);
   for (int k = threadIdx.x; k < nhot_lds; k += kBlock) touched[k] = 0;
   __syncthreads();
+  constexpr int U = 4;  // returning atomics in flight per thread
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const DevTile tl = tiles[tile];
     const DevSegment sg = segs[tl.seg];
     const int items = (tl.t1 - tl.t0) * bs;
-    for (int q = threadIdx.x; q < items; q += kBlock) {
-      const int t = tl.t0 + q / bs;
-      const int c = q % bs;
-      const int32_t r = seg_root(sg, ridx_hot, t);
-      const int64_t l = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
-      if (r >= 0) {
-        upd[l] = fetch_add_g(root + (int64_t)r * bs + c, leaf[l]);
-      } else if (-r - 1 >= nhot_lds) {
-        upd[l] = fetch_add_g(root + (int64_t)hot_roots[-r - 1] * bs + c, leaf[l]);
-      } else {
-        __hip_atomic_fetch_add(acc + (-r - 1) * bs + c, leaf[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        touched[-r - 1] = 1;
+    for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * U) {
+      T v[U], got[U];
+      int64_t ro[U];
+      int ldso[U];
+      int64_t l[U];
+      int32_t kind[U];  // 0 none, 1 device atomic, 2 LDS
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int q = q0 + u * kBlock;
+        kind[u] = 0;
+        if (q < items) {
+          const int t = tl.t0 + q / bs;
+          const int c = q % bs;
+          const int32_t r = seg_root(sg, ridx_hot, t);
+          l[u] = (int64_t)seg_leaf(sg, lidx, t) * bs + c;
+          v[u] = leaf[l[u]];
+          if (r >= 0 || -r - 1 >= nhot_lds) {
+            kind[u] = 1;
+            ro[u] = (int64_t)(r >= 0 ? r : hot_roots[-r - 1]) * bs + c;
+          } else {
+            kind[u] = 2;
+            ldso[u] = (-r - 1) * bs + c;
+            touched[-r - 1] = 1;
+          }
+        }
       }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (kind[u] == 1)
+          got[u] = fetch_add_g(root + ro[u], v[u]);
+        else if (kind[u] == 2)
+          __hip_atomic_fetch_add(acc + ldso[u], v[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (kind[u] == 1) upd[l[u]] = got[u];
     }
   }
   __syncthreads();
@@ -535,18 +580,24 @@ static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st
                          d.sl, leaf, root, bs);
     return check_launch();
   }
-  // small classes
-#define SF_SMALL(C, DD)                                                                                           \
-  if (!h.cls[C].empty())                                                                                         \
-    hipLaunchKernelGGL((k_det_small<T, OP, DD>), dim3(nblocks((int64_t)h.cls[C].size() * bs)), dim3(kBlock), 0, \
-                       st, d.cls[C], (int)h.cls[C].size(), d.troot, d.toff, d.sl, leaf, root, bs);
-  SF_SMALL(0, 1)
-  SF_SMALL(1, 2)
-  SF_SMALL(2, 4)
-  SF_SMALL(3, 8)
-  SF_SMALL(4, 16)
-  SF_SMALL(5, 32)
-#undef SF_SMALL
+  // all small classes in one launch, NV elements per thread when the unit
+  // and the buffers allow vector accesses
+  if (!h.small_all.empty()) {
+    const uintptr_t al = (uintptr_t)leaf | (uintptr_t)root;
+    const int cnt = (int)h.small_all.size();
+    int nv = 1;
+    if (sizeof(T) * 4 <= 16 && bs % 4 == 0 && al % (sizeof(T) * 4) == 0) nv = 4;
+    else if (sizeof(T) * 2 <= 16 && bs % 2 == 0 && al % (sizeof(T) * 2) == 0) nv = 2;
+    if (nv == 4)
+      hipLaunchKernelGGL((k_det_small_all<T, OP, (sizeof(T) <= 4 ? 4 : 1)>), dim3(nblocks((int64_t)cnt * (bs / 4))),
+                         dim3(kBlock), 0, st, d.small_all, cnt, d.troot, d.toff, d.sl, leaf, root, bs);
+    else if (nv == 2)
+      hipLaunchKernelGGL((k_det_small_all<T, OP, (sizeof(T) <= 8 ? 2 : 1)>), dim3(nblocks((int64_t)cnt * (bs / 2))),
+                         dim3(kBlock), 0, st, d.small_all, cnt, d.troot, d.toff, d.sl, leaf, root, bs);
+    else
+      hipLaunchKernelGGL((k_det_small_all<T, OP, 1>), dim3(nblocks((int64_t)cnt * bs)), dim3(kBlock), 0, st,
+                         d.small_all, cnt, d.troot, d.toff, d.sl, leaf, root, bs);
+  }
   // chunk levels
   if (!h.levels.empty()) {
     const size_t need = 2 * (size_t)std::max<int64_t>(h.scratch_len, 1) * bs * sizeof(T);

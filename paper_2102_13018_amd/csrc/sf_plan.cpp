@@ -412,6 +412,7 @@ int analyze(sf_s *sf) {
     while ((1 << c) < d) c++;
     hp.cls[c].push_back((int32_t)t);
   }
+  for (int c = 0; c < kNumClasses; c++) hp.small_all.insert(hp.small_all.end(), hp.cls[c].begin(), hp.cls[c].end());
   // chunk levels of the large roots: level 0 reads leaves through sl, level
   // k > 0 reads the chunk results of level k-1.  Chunks are aligned at
   // multiples of kChunk of the root's own list, so every chunk result is a
@@ -533,6 +534,7 @@ int upload(sf_s *sf) {
   add(hp.sl.data(), hp.sl.size() * 4, (void **)&dp.sl);
   for (int c = 0; c < kNumClasses; c++) add(hp.cls[c].data(), hp.cls[c].size() * 4, (void **)&dp.cls[c]);
   add(hp.large.data(), hp.large.size() * 4, (void **)&dp.large);
+  add(hp.small_all.data(), hp.small_all.size() * 4, (void **)&dp.small_all);
   dp.levels.assign(hp.levels.size(), nullptr);
   for (size_t k = 0; k < hp.levels.size(); k++)
     add(hp.levels[k].chunks.data(), hp.levels[k].chunks.size() * sizeof(DevChunk), (void **)&dp.levels[k]);
