@@ -58,7 +58,8 @@ struct DevSWin {  // one window of the partitioned path
   int32_t base, n;         // its units in scratch: [base, base + n)
   int32_t small0, small1;  // range in the small-root item list
   int32_t big0, big1;      // range in the chunk item list
-  int32_t pad0, pad1;
+  int32_t g0;              // its first position in the root-sorted order
+  int32_t pad;
 };
 
 struct DevChunk {  // one aligned chunk of a root's (sorted) value list
@@ -110,7 +111,7 @@ struct HostPlan {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     std::vector<DevSWin> win;
     std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
-    std::vector<uint16_t> lsrc;       // [L] by sorted position: scratch slot minus window base
+    std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start
     std::vector<int32_t> pa_dst;      // [L] pass-A tile-major, increasing scratch slot in a tile
     std::vector<uint16_t> pa_loc;     // [L] tile-local processing offset of that leaf
     std::vector<int32_t> tile_leaf0;  // [ntiles] first slot if the tile's slots are contiguous, else -1
@@ -135,7 +136,7 @@ struct DevPlan {
   struct Stage {
     DevSWin *win = nullptr;
     int32_t *small = nullptr, *big = nullptr, *pa_dst = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
-    uint16_t *lsrc = nullptr, *pa_loc = nullptr;
+    uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
 };
 

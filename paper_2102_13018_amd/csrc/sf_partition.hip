@@ -11,7 +11,8 @@
 //           contiguous run per window;
 //   pass B  loads one window -- whole small roots and aligned kChunk-leaf
 //           chunks of large roots -- from its contiguous scratch range into
-//           LDS and evaluates the canonical pairwise trees from there.
+//           LDS, putting every leaf at its root-sorted place, and evaluates
+//           the canonical pairwise trees from there.
 // The trees are the same as those of the direct kernels, so results are
 // bit-identical to them (and to the oracle).  FetchAndOp writes the fetched
 // values back into the window (pass B) and moves them to leafupdate with
@@ -76,29 +77,44 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const int32_t *__rest
   }
 }
 
-// Load / store one window's units between scratch and LDS (element type T).
+// Load one window from scratch into LDS in root-sorted order (LDS offset =
+// sorted position - window start), and store it back.  Global accesses are
+// coalesced; the permutation happens in LDS.
 template <typename T>
-__device__ __forceinline__ void win_load(T *lds, const T *__restrict__ scr, const DevSWin &w, int bs) {
-  const int items = w.n * bs;
+__device__ __forceinline__ void win_load(T *lds, const T *__restrict__ scr, const uint16_t *__restrict__ lpos,
+                                         const DevSWin &w, int bs) {
   const T *src = scr + (int64_t)w.base * bs;
+  if (bs == 1) {
 #pragma unroll 8
-  for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = src[q];
+    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q]] = src[q];
+  } else {
+    const int items = w.n * bs;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < items; q += kStageThreads) {
+      const int k = q / bs;
+      lds[(int)lpos[w.base + k] * bs + (q - k * bs)] = src[q];
+    }
+  }
 }
 template <typename T>
-__device__ __forceinline__ void win_store(const T *lds, T *__restrict__ scr, const DevSWin &w, int bs) {
-  const int items = w.n * bs;
+__device__ __forceinline__ void win_store(const T *lds, T *__restrict__ scr, const uint16_t *__restrict__ lpos,
+                                          const DevSWin &w, int bs) {
   T *dst = scr + (int64_t)w.base * bs;
-#pragma unroll 8
-  for (int q = threadIdx.x; q < items; q += kStageThreads) dst[q] = lds[q];
+  const int items = w.n * bs;
+#pragma unroll 4
+  for (int q = threadIdx.x; q < items; q += kStageThreads) {
+    const int k = q / bs;
+    dst[q] = lds[(int)lpos[w.base + k] * bs + (q - k * bs)];
+  }
 }
 
-// Pairwise tree over n <= D values of one root, read from LDS.
+// Pairwise tree over the n <= D consecutive (sorted) values at LDS offset o.
 template <typename T, int OP, int D>
-__device__ __forceinline__ T lds_tree(const T *lds, const uint16_t *__restrict__ lsrc, int g0, int n, int bs, int c) {
+__device__ __forceinline__ T lds_tree(const T *lds, int o, int n, int bs, int c) {
   T x[D];
 #pragma unroll
   for (int p = 0; p < D; p++)
-    if (p < n) x[p] = ld(lds + (int)lsrc[g0 + p] * bs + c);
+    if (p < n) x[p] = ld(lds + (o + p) * bs + c);
 #pragma unroll
   for (int d = 1; d < D; d *= 2)
 #pragma unroll
@@ -115,13 +131,13 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
                                                              const DevChunk *__restrict__ chunks0,
                                                              const int32_t *__restrict__ troot,
                                                              const int32_t *__restrict__ toff,
-                                                             const uint16_t *__restrict__ lsrc,
+                                                             const uint16_t *__restrict__ lpos,
                                                              const T *__restrict__ scr, T *__restrict__ lvl_out,
                                                              T *__restrict__ root, int bs) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
   const DevSWin win = wins[blockIdx.x];
-  win_load(lds, scr, win, bs);
+  win_load(lds, scr, lpos, win, bs);
   __syncthreads();
   // whole roots of degree <= kSmallMaxDeg: one thread per (root, element)
   const int nsmall = (win.small1 - win.small0) * bs;
@@ -130,19 +146,20 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
     const int t = small[win.small0 + k];
     const int g0 = toff[t];
     const int n = toff[t + 1] - g0;
+    const int o = g0 - win.g0;
     T v;
     if (n <= 1)
-      v = lds_tree<T, OP, 1>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 1>(lds, o, n, bs, c);
     else if (n <= 2)
-      v = lds_tree<T, OP, 2>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 2>(lds, o, n, bs, c);
     else if (n <= 4)
-      v = lds_tree<T, OP, 4>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 4>(lds, o, n, bs, c);
     else if (n <= 8)
-      v = lds_tree<T, OP, 8>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 8>(lds, o, n, bs, c);
     else if (n <= 16)
-      v = lds_tree<T, OP, 16>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 16>(lds, o, n, bs, c);
     else
-      v = lds_tree<T, OP, 32>(lds, lsrc, g0, n, bs, c);
+      v = lds_tree<T, OP, 32>(lds, o, n, bs, c);
     T *rp = root + (int64_t)troot[t] * bs + c;
     st(rp, Op<OP, T>::apply(ld(rp), v));
   }
@@ -151,18 +168,13 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
     const DevChunk ch = chunks0[big[ci]];
-    int idx[LPT];
-#pragma unroll
-    for (int s = 0; s < LPT; s++) {
-      const int e = lane * LPT + s;
-      idx[s] = e < ch.n ? (int)lsrc[ch.src + e] : 0;
-    }
+    const int o = ch.src - win.g0 + lane * LPT;
     const int m = ch.n - lane * LPT;
     for (int c = 0; c < bs; c++) {
       T x[LPT];
 #pragma unroll
       for (int s = 0; s < LPT; s++)
-        if (s < m) x[s] = ld(lds + idx[s] * bs + c);
+        if (s < m) x[s] = ld(lds + (o + s) * bs + c);
 #pragma unroll
       for (int d = 1; d < LPT; d *= 2)
 #pragma unroll
@@ -171,8 +183,8 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
       T v = x[0];
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
-        const T o = shfl_down(v, d);
-        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < ch.n) v = Op<OP, T>::apply(v, o);
+        const T o2 = shfl_down(v, d);
+        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < ch.n) v = Op<OP, T>::apply(v, o2);
       }
       if (lane == 0) {
         if (ch.dst < 0) {
@@ -196,22 +208,22 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_b1(const DevSWin *__re
                                                              const DevChunk *__restrict__ fo_chunks,
                                                              const int32_t *__restrict__ troot,
                                                              const int32_t *__restrict__ toff,
-                                                             const uint16_t *__restrict__ lsrc, T *__restrict__ scr,
+                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
                                                              T *__restrict__ sums, T *__restrict__ root, int bs) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
   const DevSWin win = wins[blockIdx.x];
-  win_load(lds, scr, win, bs);
+  win_load(lds, scr, lpos, win, bs);
   __syncthreads();
   const int nsmall = (win.small1 - win.small0) * bs;
   for (int q = threadIdx.x; q < nsmall; q += kStageThreads) {
     const int k = q / bs, c = q - (q / bs) * bs;
     const int t = small[win.small0 + k];
-    const int g0 = toff[t], g1 = toff[t + 1];
+    const int o0 = toff[t] - win.g0, o1 = toff[t + 1] - win.g0;
     T *rp = root + (int64_t)troot[t] * bs + c;
     T a = *rp;
-    for (int g = g0; g < g1; g++) {
-      T *e = lds + (int)lsrc[g] * bs + c;
+    for (int o = o0; o < o1; o++) {
+      T *e = lds + o * bs + c;
       const T v = *e;
       *e = a;
       a = Op<OP_SUM, T>::apply(a, v);
@@ -223,20 +235,19 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_b1(const DevSWin *__re
   for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
     const int k = big[ci];
     const DevChunk ch = fo_chunks[k];
+    const int o = ch.src - win.g0 + lane * LPT;
     for (int c = 0; c < bs; c++) {
       T a = T(0);
 #pragma unroll
-      for (int s = 0; s < LPT; s++) {
-        const int e = lane * LPT + s;
-        if (e < ch.n) a = Op<OP_SUM, T>::apply(a, lds[(int)lsrc[ch.src + e] * bs + c]);
-      }
+      for (int s = 0; s < LPT; s++)
+        if (lane * LPT + s < ch.n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
 #pragma unroll
       for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
       if (lane == 0) sums[(int64_t)k * bs + c] = a;
     }
   }
   __syncthreads();
-  if (win.small1 > win.small0) win_store(lds, scr, win, bs);
+  if (win.small1 > win.small0) win_store(lds, scr, lpos, win, bs);
 }
 
 // B3: chunks of large roots: exclusive prefix inside the chunk plus the
@@ -245,49 +256,45 @@ template <typename T>
 __global__ __launch_bounds__(kStageThreads) void k_sp_fop_b3(const DevSWin *__restrict__ wins,
                                                              const int32_t *__restrict__ big,
                                                              const DevChunk *__restrict__ fo_chunks,
-                                                             const uint16_t *__restrict__ lsrc, T *__restrict__ scr,
+                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
                                                              const T *__restrict__ sums, int bs) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
   const DevSWin win = wins[blockIdx.x];
   if (win.big1 == win.big0) return;
-  win_load(lds, scr, win, bs);
+  win_load(lds, scr, lpos, win, bs);
   __syncthreads();
   constexpr int LPT = kChunkLPT;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
     const int k = big[ci];
     const DevChunk ch = fo_chunks[k];
-    int li[LPT];
-#pragma unroll
-    for (int s = 0; s < LPT; s++) {
-      const int e = lane * LPT + s;
-      li[s] = e < ch.n ? (int)lsrc[ch.src + e] : -1;
-    }
+    const int o = ch.src - win.g0 + lane * LPT;
+    const int m = ch.n - lane * LPT;
     for (int c = 0; c < bs; c++) {
       T x[LPT];
       T lane_sum = T(0);
 #pragma unroll
       for (int s = 0; s < LPT; s++) {
-        x[s] = li[s] >= 0 ? lds[li[s] * bs + c] : T(0);
+        x[s] = s < m ? lds[(o + s) * bs + c] : T(0);
         lane_sum = Op<OP_SUM, T>::apply(lane_sum, x[s]);
       }
       T inc = lane_sum;
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
-        const T o = shfl_up(inc, d);
-        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
+        const T o2 = shfl_up(inc, d);
+        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o2);
       }
       T a = Op<OP_SUM, T>::apply(sums[(int64_t)k * bs + c], wrap_sub(inc, lane_sum));
 #pragma unroll
       for (int s = 0; s < LPT; s++) {
-        if (li[s] >= 0) lds[li[s] * bs + c] = a;
+        if (s < m) lds[(o + s) * bs + c] = a;
         a = Op<OP_SUM, T>::apply(a, x[s]);
       }
     }
   }
   __syncthreads();
-  win_store(lds, scr, win, bs);
+  win_store(lds, scr, lpos, win, bs);
 }
 
 // ================================================================ launchers
@@ -353,7 +360,7 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st)
   if (rc) return rc;
   const DevChunk *c0 = h.levels.empty() ? nullptr : d.levels[0];
   hipLaunchKernelGGL((k_sp_reduce<T, OP>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds, st, ds.win,
-                     ds.small, ds.big, c0, d.troot, d.toff, ds.lsrc, (const T *)scr, buf[0], root, bs);
+                     ds.small, ds.big, c0, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0], root, bs);
   for (size_t k = 1; k < h.levels.size(); k++) {
     const int nch = (int)h.levels[k].chunks.size();
     hipLaunchKernelGGL((k_det_chunk<T, OP>), dim3((unsigned)((nch * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
@@ -385,12 +392,12 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_
   if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, lds))) return rc;
   if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, lds))) return rc;
   hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.small, ds.big, d.fo_chunks,
-                     d.troot, d.toff, ds.lsrc, scr, sums, root, bs);
+                     d.troot, d.toff, ds.lpos, scr, sums, root, bs);
   if (nch) {
     hipLaunchKernelGGL((k_fop_root_scan<T>), dim3(nlarge), dim3(kBlock), 0, st, d.fo_root_first, nlarge,
                        d.fo_chunks, sums, root, bs);
     hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.big, d.fo_chunks,
-                       ds.lsrc, scr, (const T *)sums, bs);
+                       ds.lpos, scr, (const T *)sums, bs);
   }
   rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
   if (rc) return rc;

@@ -111,8 +111,9 @@ static DevPattern to_dev(const sf_pattern &p) {
 //  * pass A, which moves the leaves of `ta` consecutive processing positions
 //    (one pass-A tile) into scratch, writes one contiguous run per window,
 //    in increasing slot order (pa_dst / pa_loc);
-//  * pass B loads one window's contiguous scratch range into LDS and reads
-//    the g-th sorted leaf at LDS offset lsrc[g].
+//  * pass B loads one window's contiguous scratch range into LDS, moving
+//    scratch slot s to LDS offset lpos[s] (its sorted position minus the
+//    window's first sorted position).
 static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int32_t> &perm,
                        const std::vector<int64_t> &proc_leaf, const std::vector<int32_t> &proc_slot, int64_t L,
                        int32_t ta, int32_t cap) {
@@ -170,6 +171,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   int64_t base = 0;
   for (int64_t w = 0; w < W; w++) {
     sp.win[w].base = (int32_t)base;
+    sp.win[w].g0 = (int32_t)base;  // windows cover the sorted order in order
     base += sp.win[w].n;
   }
   if (base != L || chunk != (int32_t)lv0.size() || lv0.size() != hp.fo_chunks.size()) return SF_ERR_ARG;
@@ -184,11 +186,12 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     proc_of_leaf[i] = (int32_t)p;
     dst[p] = cursor[win_g[pos[i]]]++;
   }
-  sp.lsrc.resize(L);
+  sp.lpos.assign(L, 0);
   for (int64_t g = 0; g < L; g++) {
-    const int64_t off = dst[proc_of_leaf[perm[g]]] - (int64_t)sp.win[win_g[g]].base;
-    if (off < 0 || off >= sp.win[win_g[g]].n || off > 65535) return SF_ERR_ARG;
-    sp.lsrc[g] = (uint16_t)off;
+    const DevSWin &w = sp.win[win_g[g]];
+    const int64_t s = dst[proc_of_leaf[perm[g]]];
+    if (s < w.base || s >= (int64_t)w.base + w.n || g - w.g0 > 65535) return SF_ERR_ARG;
+    sp.lpos[s] = (uint16_t)(g - w.g0);
   }
   // pass-A tiles: increasing scratch slot inside each tile
   const int64_t ntiles = (L + ta - 1) / ta;
@@ -546,7 +549,7 @@ int upload(sf_s *sf) {
     add(sp.win.data(), sp.win.size() * sizeof(DevSWin), (void **)&ds.win);
     add(sp.small.data(), sp.small.size() * 4, (void **)&ds.small);
     add(sp.big.data(), sp.big.size() * 4, (void **)&ds.big);
-    add(sp.lsrc.data(), sp.lsrc.size() * 2, (void **)&ds.lsrc);
+    add(sp.lpos.data(), sp.lpos.size() * 2, (void **)&ds.lpos);
     add(sp.pa_dst.data(), sp.pa_dst.size() * 4, (void **)&ds.pa_dst);
     add(sp.pa_loc.data(), sp.pa_loc.size() * 2, (void **)&ds.pa_loc);
     add(sp.tile_leaf0.data(), sp.tile_leaf0.size() * 4, (void **)&ds.tile_leaf0);
