@@ -253,7 +253,7 @@ def batch_row(torch, S, inputs, steps):
         rng = np.random.default_rng(it["seed"])
         tt, sd, es = tdt[it["dtype"]]
         bs = it["bs"]
-        sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="atomic")
+        sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="auto")
         root = torch.from_numpy(inputs.unit_data(rng, g.nroots, bs, it["dtype"])).to(dev)
         leaf = torch.from_numpy(inputs.unit_data(rng, g.nleaves, bs, it["dtype"])).to(dev)
         deg = np.bincount(g.iroot, minlength=g.nroots)

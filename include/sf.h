@@ -28,6 +28,8 @@
  *    pointer and returns SF_ERR_ARG for memory that is not device memory.
  *  - Device indices are 32-bit: nroots and the leaf space must be < 2^31.
  *  - An SF and its scratch memory may be used by one stream at a time.
+ *  - sf_setup uploads the plan to the current device; *_begin returns
+ *    SF_ERR_ARG when called with another device current.
  */
 #ifndef SF_H
 #define SF_H
@@ -76,8 +78,9 @@ typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4
 
 /* How SFReduce combines leaves of a root that has several (Section 5.3 uses
  * atomics when destinations repeat).
- *  AUTO          : atomic for order-free ops and FP SUM, deterministic for
- *                  MAXLOC and REPLACE;
+ *  AUTO          : the deterministic path (measured as fast as or faster
+ *                  than the atomic one); FetchAndOp on FP units and batch
+ *                  items with roots of more than 256 leaves use atomics;
  *  ATOMIC        : native atomics, with block-local aggregation of the
  *                  roots of highest degree; FP SUM order is unspecified;
  *  DETERMINISTIC : root-sorted segmented reduction; FP SUM is the

@@ -113,6 +113,8 @@ extern "C" int sf_set_reduce_mode(sf_t sf, int32_t mode) {
 static int begin_common(sf_t sf, int kind, sf_unit unit, int32_t op, const void *a, const void *b, const void *c) {
   if (!sf) return SF_ERR_ARG;
   if (!sf->setup) return SF_ERR_NOT_SETUP;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != sf->device) return SF_ERR_ARG;  // plan lives on sf->device
   if (!valid_unit(unit)) return SF_ERR_ARG;
   if (op < SF_REPLACE || op > SF_MAXLOC) return SF_ERR_ARG;
   if (op == SF_MAXLOC && unit.dtype != SF_F64_I32) return SF_ERR_UNSUPPORTED;

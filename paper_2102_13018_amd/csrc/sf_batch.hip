@@ -36,7 +36,9 @@ struct BatchItemDev {
   void *leaf;
   int32_t dtype, bs, words;  // words: W of the move kinds
   int32_t plain;             // reduce without duplicate roots
-  uint64_t magic_words, magic_bs;
+  int32_t nv;                // elements per vector access of the deterministic reduce
+  int32_t pad;
+  uint64_t magic_words, magic_bs, magic_nvg;  // divisions by words, bs, bs / nv
 };
 
 struct BatchTile {
@@ -113,32 +115,44 @@ __device__ __forceinline__ void bw_red_atomic(const BatchItemDev &it, const Batc
 }
 
 // Deterministic SUM of one degree class: the same register tree as the
-// single-SF kernel (canonical pairwise order, root added last).
-template <typename T, int D>
+// single-SF kernel (canonical pairwise order, root added last), NV
+// consecutive elements per thread.
+template <typename T, int D, int NV>
 __device__ __forceinline__ void bw_det_class(const BatchItemDev &it, const BatchTile &bt) {
   const int bs = it.bs;
-  const int items = (bt.t1 - bt.t0) * bs;
+  const int ng = bs / NV;
+  const int items = (bt.t1 - bt.t0) * ng;
   const T *leaf = (const T *)it.leaf;
   T *root = (T *)it.root;
   const int32_t *cls = it.cls[bt.cls];
   for (int q = threadIdx.x; q < items; q += kBlock) {
-    const int kk = fdiv(q, it.magic_bs);
-    const int c = q - kk * bs;
+    const int kk = fdiv(q, it.magic_nvg);
+    const int c = (q - kk * ng) * NV;
     const int t = cls[bt.t0 + kk];
     const int g0 = it.toff[t];
     const int n = it.toff[t + 1] - g0;
-    T x[D];
+    Vec<T, NV> x[D];
 #pragma unroll
     for (int p = 0; p < D; p++)
-      if (p < n) x[p] = leaf[(int64_t)it.sl[g0 + p] * bs + c];
+      if (p < n) x[p] = vld<T, NV>(leaf + (int64_t)it.sl[g0 + p] * bs + c);
 #pragma unroll
     for (int d = 1; d < D; d *= 2)
 #pragma unroll
       for (int p = 0; p + d < D; p += 2 * d)
-        if (p + d < n) x[p] = Op<OP_SUM, T>::apply(x[p], x[p + d]);
+        if (p + d < n) x[p] = vop<OP_SUM, T, NV>(x[p], x[p + d]);
     T *rp = root + (int64_t)it.troot[t] * bs + c;
-    *rp = Op<OP_SUM, T>::apply(*rp, x[0]);
+    vst<T, NV>(rp, vop<OP_SUM, T, NV>(vld<T, NV>(rp), x[0]));
   }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void bw_det_class_nv(const BatchItemDev &it, const BatchTile &bt) {
+  if (it.nv == 4)
+    bw_det_class<T, D, (sizeof(T) <= 4 ? 4 : 1)>(it, bt);
+  else if (it.nv == 2)
+    bw_det_class<T, D, (sizeof(T) <= 8 ? 2 : 1)>(it, bt);
+  else
+    bw_det_class<T, D, 1>(it, bt);
 }
 
 // Deterministic SUM of roots with kSmallMaxDeg < degree <= kChunk: one
@@ -187,12 +201,12 @@ __device__ __forceinline__ void bw_reduce(const BatchItemDev &it, const BatchTil
     bw_det_wave<T>(it, bt);
   } else {
     switch (bt.cls) {
-      case 0: bw_det_class<T, 1>(it, bt); break;
-      case 1: bw_det_class<T, 2>(it, bt); break;
-      case 2: bw_det_class<T, 4>(it, bt); break;
-      case 3: bw_det_class<T, 8>(it, bt); break;
-      case 4: bw_det_class<T, 16>(it, bt); break;
-      default: bw_det_class<T, 32>(it, bt); break;
+      case 0: bw_det_class_nv<T, 1>(it, bt); break;
+      case 1: bw_det_class_nv<T, 2>(it, bt); break;
+      case 2: bw_det_class_nv<T, 4>(it, bt); break;
+      case 3: bw_det_class_nv<T, 8>(it, bt); break;
+      case 4: bw_det_class_nv<T, 16>(it, bt); break;
+      default: bw_det_class_nv<T, 32>(it, bt); break;
     }
   }
 }
@@ -251,7 +265,9 @@ static int batch_build_tiles(sf_batch_s *b) {
       }
       continue;
     }
-    const bool det = sf->has_dup_roots && sf->reduce_mode == SF_REDUCE_DETERMINISTIC;
+    // duplicate roots: deterministic unless the SF asks for atomics (no
+    // atomics at all, and the sum is bit-reproducible)
+    const bool det = sf->has_dup_roots && sf->reduce_mode != SF_REDUCE_ATOMIC && sf->max_degree <= kChunk;
     if (!det) {
       for (size_t s = 0; s < sf->hp.dsegs.size(); s++) {
         const int n = sf->hp.dsegs[s].n;
@@ -313,6 +329,11 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
       delete b;
       return sf ? SF_ERR_NOT_SETUP : SF_ERR_ARG;
     }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != sf->device) {  // every plan must live on this device
+      delete b;
+      return SF_ERR_ARG;
+    }
     const int es = elem_size(it.unit.dtype);
     if (es <= 0 || it.unit.bs < 1 || it.unit.dtype == SF_F64_I32 || es * (int64_t)it.unit.bs > 4096) {
       delete b;
@@ -328,7 +349,7 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
       return SF_ERR_ARG;
     }
     if (it.kind == SF_KIND_REDUCE && sf->has_dup_roots && sf->reduce_mode == SF_REDUCE_DETERMINISTIC &&
-        sf->max_degree > kChunk) {
+        sf->max_degree > kChunk) {  // AUTO falls back to atomics there
       delete b;
       return SF_ERR_UNSUPPORTED;
     }
@@ -352,6 +373,13 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
     d.words = (int32_t)(ub % 16 == 0 && a % 16 == 0 ? ub / 16 : (ub % 8 == 0 && a % 8 == 0 ? ub / 8 : ub / 4));
     d.magic_words = magic_of((uint32_t)d.words);
     d.magic_bs = magic_of((uint32_t)d.bs);
+    {
+      const uintptr_t al = (uintptr_t)it.rootdata | (uintptr_t)it.leafdata;
+      d.nv = 1;
+      if (es * 4 <= 16 && d.bs % 4 == 0 && al % (size_t)(es * 4) == 0) d.nv = 4;
+      else if (es * 2 <= 16 && d.bs % 2 == 0 && al % (size_t)(es * 2) == 0) d.nv = 2;
+      d.magic_nvg = magic_of((uint32_t)(d.bs / d.nv));
+    }
     b->items.push_back(it);
     b->hitems.push_back(d);
   }

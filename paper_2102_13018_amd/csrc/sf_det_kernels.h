@@ -55,29 +55,28 @@ __global__ __launch_bounds__(kBlock) void k_det_chunk(const DevChunk *__restrict
   }
 }
 
-// Large roots, pass 2: one block per large root turns its chunk sums into
-// chunk bases (root value + exclusive prefix) and writes the final root.
-// Each iteration scans kBlock*4 chunk sums: 4 per thread in registers, the
-// threads' totals across the wavefront with shuffles, the 4 wavefront totals
-// through LDS.
+// Large roots, pass 2: one wavefront per large root turns its chunk sums
+// into chunk bases (root value + exclusive prefix) and writes the final
+// root.  Each iteration scans 64*kScanPer chunk sums: kScanPer consecutive
+// ones per lane in registers, the lane totals with shuffles.
+constexpr int kScanPer = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fop_root_scan(const int32_t *__restrict__ first, int nlarge,
                                                           const DevChunk *__restrict__ chunks, T *__restrict__ sums,
                                                           T *__restrict__ root, int bs) {
-  __shared__ T wtot[kBlock / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int k = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int k = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
   if (k >= nlarge) return;
   const int c0 = first[k], c1 = first[k + 1];
   const int32_t r = chunks[c0].dst;
   for (int c = 0; c < bs; c++) {
     T carry = root[(int64_t)r * bs + c];
-    for (int base = c0; base < c1; base += kBlock * 4) {
-      T x[4];
+    for (int base = c0; base < c1; base += 64 * kScanPer) {
+      T x[kScanPer];
       T s = T(0);
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i = base + threadIdx.x * 4 + j;
+      for (int j = 0; j < kScanPer; j++) {
+        const int i = base + lane * kScanPer + j;
         x[j] = i < c1 ? sums[(int64_t)i * bs + c] : T(0);
         s = Op<OP_SUM, T>::apply(s, x[j]);
       }
@@ -87,23 +86,16 @@ __global__ __launch_bounds__(kBlock) void k_fop_root_scan(const int32_t *__restr
         const T o = shfl_up(inc, d);
         if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
       }
-      if (lane == 63) wtot[wv] = inc;
-      __syncthreads();
-      T before = carry;
-      for (int w = 0; w < wv; w++) before = Op<OP_SUM, T>::apply(before, wtot[w]);
-      T total = carry;
-      for (int w = 0; w < kBlock / 64; w++) total = Op<OP_SUM, T>::apply(total, wtot[w]);
-      T a = Op<OP_SUM, T>::apply(before, wrap_sub(inc, s));
+      T a = Op<OP_SUM, T>::apply(carry, wrap_sub(inc, s));
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i = base + threadIdx.x * 4 + j;
+      for (int j = 0; j < kScanPer; j++) {
+        const int i = base + lane * kScanPer + j;
         if (i < c1) sums[(int64_t)i * bs + c] = a;
         a = Op<OP_SUM, T>::apply(a, x[j]);
       }
-      carry = total;
-      __syncthreads();
+      carry = Op<OP_SUM, T>::apply(carry, __shfl(inc, 63));
     }
-    if (threadIdx.x == 0) root[(int64_t)r * bs + c] = carry;
+    if (lane == 0) root[(int64_t)r * bs + c] = carry;
   }
 }
 

@@ -662,7 +662,7 @@ static int reduce_t(sf_s *sf, int op, int mode, const void *leafv, void *rootv, 
 #define SF_RED(OPV)                                                        \
   do {                                                                     \
     if (!dup) return reduce_plain_t<T, OPV>(sf, leaf, root, bs, st);       \
-    if (mode == SF_REDUCE_DETERMINISTIC) return reduce_det_t<T, OPV>(sf, leaf, root, bs, st); \
+    if (mode != SF_REDUCE_ATOMIC) return reduce_det_t<T, OPV>(sf, leaf, root, bs, st); \
     return reduce_atomic_t<T, OPV>(sf, leaf, root, bs, st);                \
   } while (0)
   switch (op) {
@@ -734,7 +734,7 @@ static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream
     T *sums = (T *)sf->scratch;
     hipLaunchKernelGGL((k_fop_chunk_sum<T>), dim3(nblocks((int64_t)nch * 64)), dim3(kBlock), 0, st, d.fo_chunks, nch,
                        d.sl, leaf, sums, bs);
-    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3(nlarge), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        d.fo_root_first, nlarge, d.fo_chunks, sums, root, bs);
     hipLaunchKernelGGL((k_fop_chunk_apply<T>), dim3(nblocks((int64_t)nch * 64)), dim3(kBlock), 0, st, d.fo_chunks, nch,
                        d.sl, leaf, sums, upd, bs);

@@ -18,6 +18,8 @@
 // values back into the window (pass B) and moves them to leafupdate with
 // the reverse of pass A (pass C).
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "sf_det_kernels.h"
 
@@ -303,11 +305,22 @@ static int sp_check() {
   return e == hipSuccess ? SF_OK : set_hip_error(e);
 }
 
-// Allow a kernel more than the default 64 KB of dynamic LDS.
+// Allow a kernel more than the default 64 KB of dynamic LDS.  The largest
+// size granted so far is remembered per kernel and device, so the attribute
+// is set once rather than on every launch.
 static int allow_lds(const void *fn, size_t bytes) {
   if (bytes <= 65536) return SF_OK;
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void *, int>, size_t>> granted;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  for (auto &x : granted)
+    if (x.first.first == fn && x.first.second == dev && x.second >= bytes) return SF_OK;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return e == hipSuccess ? SF_OK : set_hip_error(e);
+  if (e != hipSuccess) return set_hip_error(e);
+  granted.push_back({{fn, dev}, bytes});
+  return SF_OK;
 }
 
 int stage_class(int64_t unit_bytes) { return unit_bytes <= 8 ? 0 : (unit_bytes <= 16 ? 1 : -1); }
@@ -394,7 +407,7 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_
   hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.small, ds.big, d.fo_chunks,
                      d.troot, d.toff, ds.lpos, scr, sums, root, bs);
   if (nch) {
-    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3(nlarge), dim3(kBlock), 0, st, d.fo_root_first, nlarge,
+    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d.fo_root_first, nlarge,
                        d.fo_chunks, sums, root, bs);
     hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.big, d.fo_chunks,
                        ds.lpos, scr, (const T *)sums, bs);
