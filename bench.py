@@ -162,6 +162,46 @@ def time_ops(torch, ops, steps, warmup):
     return wall
 
 
+def cold_ops(torch, ops, reps=10):
+    """Each op timed alone after flushing the 256 MB Infinity Cache (a 1 GiB
+    fill between reps); median of `reps` event-timed runs."""
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    out = {}
+    for op in ops:
+        op.fn()
+        ts = []
+        for _ in range(reps):
+            flush.fill_(1.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            op.fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        med = float(np.median(ts))
+        out[op.name] = {"us": round(med * 1e3, 1), "GBps": round(op.nbytes / med / 1e6, 1)}
+    del flush
+    return out
+
+
+def copy_ceiling(torch, nbytes=1 << 31):
+    """Measured device-to-device copy rate (read + write bytes / time)."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(5):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    return round(2 * nbytes / float(np.min(ts)) / 1e6, 1)
+
+
 def cpu_baseline(g, budget_s=12.0):
     """The oracle, as it stands, on the same SF: Bcast, Reduce SUM and
     FetchAndOp (sequential C, one thread).  Runs ops until the budget is
@@ -404,7 +444,9 @@ def main():
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
                       "parallelism": "single-gpu"},
-           "ops": per_op, "roofline": roofline}
+           "ops": per_op, "roofline": roofline,
+           "ops_cold_cache": cold_ops(torch, ops),
+           "copy_ceiling_GBps": copy_ceiling(torch)}
     if not args.no_rows:
         for name, fn in (("halo", halo_row), ("batch", batch_row), ("autograd", autograd_row)):
             try:

@@ -141,29 +141,55 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
   const DevSWin win = wins[blockIdx.x];
   win_load(lds, scr, lpos, win, bs);
   __syncthreads();
-  // whole roots of degree <= kSmallMaxDeg: one thread per (root, element)
+  // whole roots of degree <= kSmallMaxDeg: one thread per (root, element),
+  // U of them at a time so that their dependent index and root loads overlap
   const int nsmall = (win.small1 - win.small0) * bs;
-  for (int q = threadIdx.x; q < nsmall; q += kStageThreads) {
-    const int k = q / bs, c = q - (q / bs) * bs;
-    const int t = small[win.small0 + k];
-    const int g0 = toff[t];
-    const int n = toff[t + 1] - g0;
-    const int o = g0 - win.g0;
-    T v;
-    if (n <= 1)
-      v = lds_tree<T, OP, 1>(lds, o, n, bs, c);
-    else if (n <= 2)
-      v = lds_tree<T, OP, 2>(lds, o, n, bs, c);
-    else if (n <= 4)
-      v = lds_tree<T, OP, 4>(lds, o, n, bs, c);
-    else if (n <= 8)
-      v = lds_tree<T, OP, 8>(lds, o, n, bs, c);
-    else if (n <= 16)
-      v = lds_tree<T, OP, 16>(lds, o, n, bs, c);
-    else
-      v = lds_tree<T, OP, 32>(lds, o, n, bs, c);
-    T *rp = root + (int64_t)troot[t] * bs + c;
-    st(rp, Op<OP, T>::apply(ld(rp), v));
+  constexpr int U = 4;
+  for (int q0 = threadIdx.x; q0 < nsmall; q0 += kStageThreads * U) {
+    int t[U], o[U], n[U];
+    int64_t rp[U];
+    T rv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int q = q0 + u * kStageThreads;
+      n[u] = 0;
+      if (q < nsmall) {
+        const int k = q / bs;
+        t[u] = small[win.small0 + k];
+        rp[u] = q - k * bs;  // element, completed below
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (q0 + u * kStageThreads < nsmall) {
+        const int g0 = toff[t[u]];
+        n[u] = toff[t[u] + 1] - g0;
+        o[u] = g0 - win.g0;
+        rp[u] += (int64_t)troot[t[u]] * bs;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (n[u] > 0) rv[u] = ld(root + rp[u]);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (n[u] == 0) continue;
+      const int c = (int)(rp[u] % bs);
+      T v;
+      if (n[u] <= 1)
+        v = lds_tree<T, OP, 1>(lds, o[u], n[u], bs, c);
+      else if (n[u] <= 2)
+        v = lds_tree<T, OP, 2>(lds, o[u], n[u], bs, c);
+      else if (n[u] <= 4)
+        v = lds_tree<T, OP, 4>(lds, o[u], n[u], bs, c);
+      else if (n[u] <= 8)
+        v = lds_tree<T, OP, 8>(lds, o[u], n[u], bs, c);
+      else if (n[u] <= 16)
+        v = lds_tree<T, OP, 16>(lds, o[u], n[u], bs, c);
+      else
+        v = lds_tree<T, OP, 32>(lds, o[u], n[u], bs, c);
+      st(root + rp[u], Op<OP, T>::apply(rv[u], v));
+    }
   }
   // aligned chunks of larger roots: one wavefront per chunk, kChunkLPT per lane
   constexpr int LPT = kChunkLPT;
