@@ -42,19 +42,21 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
-    the summary is missing or was taken on different kernel sources."""
+def measured_traffic(op):
+    """HBM bytes per launch of `op` (all of its kernel dispatches) from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy), or None when the summary is missing or was taken on
+    different kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
         return None
-    if d.get("_source_hash") != source_hash() or kernel not in d:
+    ops = d.get("ops", {})
+    if d.get("_source_hash") != source_hash() or op not in ops:
         return None
-    return int(d[kernel]["fetch_bytes"] + d[kernel]["write_bytes"])
+    return int(ops[op]["fetch_bytes"] + ops[op]["write_bytes"])
 
 
 def parse():
@@ -76,8 +78,8 @@ def log(*a):
 
 
 class Op:
-    def __init__(self, name, fn, nbytes, kernel):
-        self.name, self.fn, self.nbytes, self.kernel = name, fn, nbytes, kernel
+    def __init__(self, name, fn, nbytes, kernels):
+        self.name, self.fn, self.nbytes, self.kernels = name, fn, nbytes, kernels
         self.times = []
 
 
@@ -92,6 +94,8 @@ def build_spmv_ops(torch, S, inputs, g):
     t0 = time.time()
     sf = S.StarForest(R, g.iroot, None, g.ranks).setup(reduce_mode="atomic")
     log(f"setup of {L} leaves: {time.time() - t0:.2f} s, info {sf.info()}")
+    # the direct persistent atomic kernels (partitioning off), timed beside the step
+    sfd = S.StarForest(R, g.iroot, None, g.ranks).setup(reduce_mode="atomic", partition="off")
 
     xr64 = torch.from_numpy(rng.standard_normal(R)).to(dev)
     xl64 = torch.from_numpy(rng.standard_normal(L)).to(dev)
@@ -110,16 +114,16 @@ def build_spmv_ops(torch, S, inputs, g):
     u64, u32 = S.SfUnit(S.SF_F64, 1), S.SfUnit(S.SF_F32, 1)
     upair, ui64 = S.SfUnit(S.SF_F64_I32, 1), S.SfUnit(S.SF_I64, 1)
 
-    def red(mode, leaf, root, op, unit):
+    def red(mode, leaf, root, op, unit, on=sf):
         def f():
-            sf.set_reduce_mode(mode)
-            sf.reduce(leaf, root, op, unit=unit)
+            on.set_reduce_mode(mode)
+            on.reduce(leaf, root, op, unit=unit)
         return f
 
-    def fop(mode):
+    def fop(mode, on=sf):
         def f():
-            sf.set_reduce_mode(mode)
-            sf.fetch_and_op(fr, fl, fu, "sum", unit=ui64)
+            on.set_reduce_mode(mode)
+            on.fetch_and_op(fr, fl, fu, "sum", unit=ui64)
         return f
 
     b8 = lambda u: L * u + Rt * u + idx            # Bcast
@@ -127,16 +131,25 @@ def build_spmv_ops(torch, S, inputs, g):
     f8 = lambda u: 2 * L * u + 2 * Rt * u + idx    # FetchAndOp
     ops = [
         Op("bcast_replace_f64", lambda: sf.bcast(xr64, yl64, "replace", unit=u64), b8(8), "k_bcast_move"),
-        Op("reduce_sum_f64_atomic", red("atomic", xl64, xr64, "sum", u64), r8(8), "k_reduce_atomic"),
-        Op("reduce_sum_f64_det", red("deterministic", xl64, xr64, "sum", u64), r8(8), "k_det_*"),
-        Op("reduce_sum_f32_det", red("deterministic", xl32, xr32, "sum", u32), r8(4), "k_det_*"),
-        Op("reduce_max_f64_atomic", red("atomic", xl64, xr64, "max", u64), r8(8), "k_reduce_atomic"),
-        Op("reduce_maxloc_det", red("deterministic", lpair, rpair, "maxloc", upair), r8(16), "k_det_*"),
-        Op("fetch_and_op_i64_det", fop("deterministic"), f8(8), "k_fop_*"),
-        Op("fetch_and_op_i64_atomic", fop("atomic"), f8(8), "k_fop_atomic_hot"),
+        Op("reduce_sum_f64_atomic", red("atomic", xl64, xr64, "sum", u64), r8(8), "k_sp_move + k_sp_reduce<atomic>"),
+        Op("reduce_sum_f64_det", red("deterministic", xl64, xr64, "sum", u64), r8(8),
+           "k_sp_move + k_sp_reduce + k_det_chunk"),
+        Op("reduce_sum_f32_det", red("deterministic", xl32, xr32, "sum", u32), r8(4),
+           "k_sp_move + k_sp_reduce + k_det_chunk"),
+        Op("reduce_max_f64_atomic", red("atomic", xl64, xr64, "max", u64), r8(8), "k_sp_move + k_sp_reduce<atomic>"),
+        Op("reduce_maxloc_det", red("deterministic", lpair, rpair, "maxloc", upair), r8(16),
+           "k_sp_move + k_sp_reduce + k_det_chunk"),
+        Op("fetch_and_op_i64_det", fop("deterministic"), f8(8),
+           "k_sp_move + k_sp_fop_b1 + k_fop_root_scan + k_sp_fop_b3 + k_sp_move"),
+        Op("fetch_and_op_i64_atomic", fop("atomic"), f8(8), "k_sp_move + k_sp_fop_atomic + k_sp_move"),
+    ]
+    direct = [
+        Op("reduce_sum_f64_atomic_direct", red("atomic", xl64, xr64, "sum", u64, sfd), r8(8), "k_reduce_atomic"),
+        Op("reduce_max_f64_atomic_direct", red("atomic", xl64, xr64, "max", u64, sfd), r8(8), "k_reduce_atomic"),
+        Op("fetch_and_op_i64_atomic_direct", fop("atomic", sfd), f8(8), "k_fop_atomic_hot"),
     ]
     data = dict(xr64=xr64, xl64=xl64, deg=deg, Rt=Rt)
-    return sf, ops, data
+    return sf, ops, direct, data
 
 
 def time_ops(torch, ops, steps, warmup):
@@ -406,10 +419,10 @@ def main():
     t0 = time.time()
     g = inputs.spmv_ghost(seed=3)
     log(f"generated spmv_ghost in {time.time() - t0:.1f} s")
-    sf, ops, data = build_spmv_ops(torch, S, inputs, g)
+    sf, ops, direct, data = build_spmv_ops(torch, S, inputs, g)
     if args.profile_op:
         names = args.profile_op.split(",")
-        ops = [o for o in ops if o.name in names]
+        ops = [o for o in ops + direct if o.name in names]
         assert len(ops) == len(names), f"unknown op in {args.profile_op}"
         time_ops(torch, ops, args.steps, args.warmup)
         for o in ops:
@@ -428,15 +441,23 @@ def main():
                           "GBps": round(o.nbytes / med / 1e6, 1),
                           "frac_peak": round(o.nbytes / med / 1e6 / HBM_PEAK_GBS, 4)}
         log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
-    # dominant single-kernel op (largest share of step time)
-    single = [o for o in ops if o.kernel in ("k_bcast_move", "k_reduce_atomic", "k_fop_atomic_hot")]
-    dom = max(single, key=lambda o: float(np.mean(o.times)))
+    # dominant op: the largest share of step time; one launch of it is one
+    # begin/end pair, i.e. the sequence of kernels named in "kernel"
+    dom = max(ops, key=lambda o: float(np.mean(o.times)))
     avg_ms = float(np.mean(dom.times))
-    roofline = {"bound": "hbm", "kernel": dom.kernel, "op": dom.name,
+    roofline = {"bound": "hbm", "kernel": dom.kernels, "op": dom.name,
                 "achieved": round(dom.nbytes / avg_ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom.nbytes / avg_ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.kernel),
+                "frac": round(dom.nbytes / avg_ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.name),
                 "alg_bytes_per_launch": dom.nbytes,
                 "avg_launch_us": round(avg_ms * 1e3, 1)}
+    # the direct persistent atomic kernels, timed alone after the step
+    time_ops(torch, direct, max(5, args.steps // 2), 2)
+    direct_row = {}
+    for o in direct:
+        med = float(np.median(o.times))
+        direct_row[o.name] = {"us": round(med * 1e3, 1), "GBps": round(o.nbytes / med / 1e6, 1),
+                              "kernel": o.kernels, "traffic": measured_traffic(o.name)}
+        log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
     out = {"metric": "effective HBM GB/s (unit data + indices) for SFBcast/SFReduce vs peak; batched vs per-SF time",
            "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -444,7 +465,7 @@ def main():
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
                       "parallelism": "single-gpu"},
-           "ops": per_op, "roofline": roofline,
+           "ops": per_op, "roofline": roofline, "row_direct_atomic": direct_row,
            "ops_cold_cache": cold_ops(torch, ops),
            "copy_ceiling_GBps": copy_ceiling(torch)}
     if not args.no_rows:

@@ -123,6 +123,10 @@ __device__ __forceinline__ int32_t shfl_up(int32_t v, int d) { return __shfl_up(
 __device__ __forceinline__ int64_t shfl_up(int64_t v, int d) { return (int64_t)__shfl_up((long long)v, d); }
 __device__ __forceinline__ double shfl_up(double v, int d) { return __shfl_up(v, d); }
 __device__ __forceinline__ float shfl_up(float v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ int32_t shfl_idx(int32_t v, int l) { return __shfl(v, l); }
+__device__ __forceinline__ int64_t shfl_idx(int64_t v, int l) { return (int64_t)__shfl((long long)v, l); }
+__device__ __forceinline__ double shfl_idx(double v, int l) { return __shfl(v, l); }
+__device__ __forceinline__ float shfl_idx(float v, int l) { return __shfl(v, l); }
 
 // Index of the t-th leaf of a segment side with a pattern (Section 5.2).
 __device__ __forceinline__ int32_t pat_index(const DevPattern &p, int32_t t) {
@@ -362,13 +366,14 @@ __device__ __forceinline__ int64_t wrap_sub(int64_t a, int64_t b) { return (int6
 }  // namespace sfi
 
 namespace sfi {
-// Launchers of the partitioned deterministic path (sf_partition.hip), and
+// Launchers of the partitioned path (sf_partition.hip), deterministic or
+// with native atomics where chunks of one root meet, and
 // its unit-size class (0: <= 8 bytes, 1: <= 16 bytes, -1: not staged).
 int stage_class(int64_t unit_bytes);
 template <typename T, int OP>
-int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st);
+int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hipStream_t st);
 template <typename T>
-int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st);
+int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomic, hipStream_t st);
 }  // namespace sfi
 
 namespace sfi {

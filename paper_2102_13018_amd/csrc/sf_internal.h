@@ -109,6 +109,7 @@ struct HostPlan {
   bool part = false;
   struct Stage {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
+    int32_t maxbig = 0;               // most level-0 chunks in one window
     std::vector<DevSWin> win;
     std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
     std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start

@@ -572,7 +572,7 @@ static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   if (OP != OP_REPLACE && h.part && stage_class((int64_t)sizeof(T) * bs) >= 0)
-    return launch_reduce_part<T, OP>(sf, leaf, root, bs, st);
+    return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
     if (T_)
@@ -627,6 +627,7 @@ template <typename T, int OP>
 static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
+  if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
   const int ntiles = (int)h.tiles.size();
   const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kReduceGrid);
   const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
@@ -705,6 +706,7 @@ template <typename T>
 static int fop_atomic_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
+  if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, true, st);
   const int ntiles = (int)h.tiles.size();
   if (!h.hot_roots.empty()) {
     const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kFetchGrid);
@@ -721,7 +723,7 @@ template <typename T>
 static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, st);
+  if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, false, st);
   for (int c = 0; c < kNumClasses; c++)
     if (!h.cls[c].empty())
       hipLaunchKernelGGL((k_fop_small<T>), dim3(nblocks((int64_t)h.cls[c].size() * bs)), dim3(kBlock), 0, st, d.cls[c],

@@ -19,6 +19,7 @@
 // the reverse of pass A (pass C).
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "sf_det_kernels.h"
@@ -125,17 +126,35 @@ __device__ __forceinline__ T lds_tree(const T *lds, int o, int n, int bs, int c)
   return x[0];
 }
 
+// Root of level-0 chunk k and whether k is its root's first (bit 0) and
+// last (bit 1) chunk, for the per-window runs of the atomic mode.
+__device__ __forceinline__ void chunk_info(const DevChunk *__restrict__ fo, int k, int nfo, int32_t *cr,
+                                           int32_t *cf) {
+  const int32_t r = fo[k].dst;
+  const int32_t prev = k > 0 ? fo[k - 1].dst : -1;
+  const int32_t next = k + 1 < nfo ? fo[k + 1].dst : -1;
+  *cr = r;
+  *cf = (prev != r ? 1 : 0) | (next != r ? 2 : 0);
+}
+
 // ------------------------------------------------------------- pass B reduce
-template <typename T, int OP>
+// ATOM: the chunk values of a root are combined per window (in chunk order,
+// in LDS after the window's values, at element offset ctot_off, followed by
+// each chunk's root and first/last flags); a root whose
+// chunks all lie in this window is then updated plainly, one that spans
+// windows through one native atomic per window, in arrival order, instead of
+// the chunk-level trees.  fo (nfo chunks) gives each chunk's root.
+template <typename T, int OP, bool ATOM>
 __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__restrict__ wins,
                                                              const int32_t *__restrict__ small,
                                                              const int32_t *__restrict__ big,
                                                              const DevChunk *__restrict__ chunks0,
+                                                             const DevChunk *__restrict__ fo,
                                                              const int32_t *__restrict__ troot,
                                                              const int32_t *__restrict__ toff,
                                                              const uint16_t *__restrict__ lpos,
                                                              const T *__restrict__ scr, T *__restrict__ lvl_out,
-                                                             T *__restrict__ root, int bs) {
+                                                             T *__restrict__ root, int bs, int ctot_off, int nfo) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
   const DevSWin win = wins[blockIdx.x];
@@ -195,7 +214,8 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
   constexpr int LPT = kChunkLPT;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
-    const DevChunk ch = chunks0[big[ci]];
+    const int k = big[ci];
+    const DevChunk ch = chunks0[k];
     const int o = ch.src - win.g0 + lane * LPT;
     const int m = ch.n - lane * LPT;
     for (int c = 0; c < bs; c++) {
@@ -215,13 +235,40 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
         if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < ch.n) v = Op<OP, T>::apply(v, o2);
       }
       if (lane == 0) {
-        if (ch.dst < 0) {
+        if constexpr (ATOM) {
+          lds[ctot_off + (ci - win.big0) * bs + c] = v;
+          if (c == 0) {
+            int32_t *cr = reinterpret_cast<int32_t *>(lds + ctot_off + (win.big1 - win.big0) * bs);
+            chunk_info(fo, k, nfo, cr + (ci - win.big0), cr + (win.big1 - win.big0) + (ci - win.big0));
+          }
+        } else if (ch.dst < 0) {
           T *rp = root + (int64_t)(-ch.dst - 1) * bs + c;
           st(rp, Op<OP, T>::apply(ld(rp), v));
         } else {
           st(lvl_out + (int64_t)ch.dst * bs + c, v);
         }
       }
+    }
+  }
+  if constexpr (ATOM) {
+    __syncthreads();
+    const T *ctot = lds + ctot_off;
+    const int nb = win.big1 - win.big0;
+    const int32_t *cr = reinterpret_cast<const int32_t *>(ctot + nb * bs);
+    const int32_t *cf = cr + nb;
+    for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+      const int j = q / bs, c = q - j * bs;
+      const int32_t r = cr[j];
+      if (j > 0 && cr[j - 1] == r) continue;  // not the first chunk of its run
+      T acc = ctot[j * bs + c];
+      int j1 = j + 1;
+      for (; j1 < nb && cr[j1] == r; j1++) acc = Op<OP, T>::apply(acc, ctot[j1 * bs + c]);
+      const bool whole = (cf[j] & 1) && (cf[j1 - 1] & 2);
+      T *rp = root + (int64_t)r * bs + c;
+      if (whole)
+        st(rp, Op<OP, T>::apply(ld(rp), acc));
+      else
+        AtomicG<OP, T>::run(rp, acc);
     }
   }
 }
@@ -325,6 +372,130 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_b3(const DevSWin *__re
   win_store(lds, scr, lpos, win, bs);
 }
 
+// ------------------------------------------------- pass B FetchAndOp, atomic
+// One pass: small roots scan in leaf order as in B1.  The chunks of a large
+// root that lie in this window form a run: their totals (in LDS after the
+// window's values, at element offset ctot_off, followed by each chunk's root
+// and first/last flags) give every chunk its offset
+// inside the run, and the run takes its base from the root -- plainly when
+// the run is the whole root, else with one native returning atomic add, so
+// the windows of a spanning root are applied in arrival order while the
+// leaves inside a window keep leaf order.
+template <typename T>
+__global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *__restrict__ wins,
+                                                                 const int32_t *__restrict__ small,
+                                                                 const int32_t *__restrict__ big,
+                                                                 const DevChunk *__restrict__ fo_chunks,
+                                                                 const int32_t *__restrict__ troot,
+                                                                 const int32_t *__restrict__ toff,
+                                                                 const uint16_t *__restrict__ lpos,
+                                                                 T *__restrict__ scr, T *__restrict__ root, int bs,
+                                                                 int ctot_off, int nfo) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *lds = reinterpret_cast<T *>(smem);
+  T *ctot = lds + ctot_off;
+  const DevSWin win = wins[blockIdx.x];
+  win_load(lds, scr, lpos, win, bs);
+  __syncthreads();
+  const int nsmall = (win.small1 - win.small0) * bs;
+  for (int q = threadIdx.x; q < nsmall; q += kStageThreads) {
+    const int k = q / bs, c = q - (q / bs) * bs;
+    const int t = small[win.small0 + k];
+    const int o0 = toff[t] - win.g0, o1 = toff[t + 1] - win.g0;
+    T *rp = root + (int64_t)troot[t] * bs + c;
+    T a = *rp;
+    for (int o = o0; o < o1; o++) {
+      T *e = lds + o * bs + c;
+      const T v = *e;
+      *e = a;
+      a = Op<OP_SUM, T>::apply(a, v);
+    }
+    *rp = a;
+  }
+  const int nb = win.big1 - win.big0;
+  if (nb == 0) {
+    __syncthreads();
+    win_store(lds, scr, lpos, win, bs);
+    return;
+  }
+  constexpr int LPT = kChunkLPT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t *cr = reinterpret_cast<int32_t *>(ctot + nb * bs);
+  int32_t *cf = cr + nb;
+  // 1: chunk totals
+  for (int j = wv; j < nb; j += kStageThreads / 64) {
+    const int kk = big[win.big0 + j];
+    const DevChunk ch = fo_chunks[kk];
+    if (lane == 0) chunk_info(fo_chunks, kk, nfo, cr + j, cf + j);
+    const int o = ch.src - win.g0 + lane * LPT;
+    for (int c = 0; c < bs; c++) {
+      T a = T(0);
+#pragma unroll
+      for (int s = 0; s < LPT; s++)
+        if (lane * LPT + s < ch.n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
+#pragma unroll
+      for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
+      if (lane == 0) ctot[j * bs + c] = a;
+    }
+  }
+  __syncthreads();
+  // 2: per run, chunk offsets inside the run and the run's base from the root
+  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+    const int j = q / bs, c = q - j * bs;
+    const int32_t r = cr[j];
+    if (j > 0 && cr[j - 1] == r) continue;  // not the first chunk of its run
+    int j1 = j;
+    T run = T(0);
+    for (; j1 < nb && cr[j1] == r; j1++) {
+      const T t = ctot[j1 * bs + c];
+      ctot[j1 * bs + c] = run;
+      run = Op<OP_SUM, T>::apply(run, t);
+    }
+    const bool whole = (cf[j] & 1) && (cf[j1 - 1] & 2);
+    T *rp = root + (int64_t)r * bs + c;
+    T base;
+    if (whole) {
+      base = *rp;
+      *rp = Op<OP_SUM, T>::apply(base, run);
+    } else {
+      base = fetch_add_g(rp, run);
+    }
+    for (int jj = j; jj < j1; jj++) ctot[jj * bs + c] = Op<OP_SUM, T>::apply(base, ctot[jj * bs + c]);
+  }
+  __syncthreads();
+  // 3: exclusive prefix inside each chunk plus the chunk's base
+  for (int j = wv; j < nb; j += kStageThreads / 64) {
+    const DevChunk ch = fo_chunks[big[win.big0 + j]];
+    const int o = ch.src - win.g0 + lane * LPT;
+    const int m = ch.n - lane * LPT;
+    for (int c = 0; c < bs; c++) {
+      T x[LPT];
+      T lane_sum = T(0);
+#pragma unroll
+      for (int s = 0; s < LPT; s++) {
+        x[s] = s < m ? lds[(o + s) * bs + c] : T(0);
+        lane_sum = Op<OP_SUM, T>::apply(lane_sum, x[s]);
+      }
+      T inc = lane_sum;
+#pragma unroll
+      for (int d = 1; d < 64; d *= 2) {
+        const T o2 = shfl_up(inc, d);
+        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o2);
+      }
+      T excl = shfl_up(inc, 1);
+      if (lane == 0) excl = T(0);
+      T a = Op<OP_SUM, T>::apply(ctot[j * bs + c], excl);
+#pragma unroll
+      for (int s = 0; s < LPT; s++) {
+        if (s < m) lds[(o + s) * bs + c] = a;
+        a = Op<OP_SUM, T>::apply(a, x[s]);
+      }
+    }
+  }
+  __syncthreads();
+  win_store(lds, scr, lpos, win, bs);
+}
+
 // ================================================================ launchers
 static int sp_check() {
   hipError_t e = hipGetLastError();
@@ -378,7 +549,7 @@ static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_
 }
 
 template <typename T, int OP>
-int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
+int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const int64_t L = sf->nleaves;
@@ -395,11 +566,24 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st)
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   const size_t lds = (size_t)hs.cap * ub;
-  rc = allow_lds((const void *)&k_sp_reduce<T, OP>, lds);
-  if (rc) return rc;
   const DevChunk *c0 = h.levels.empty() ? nullptr : d.levels[0];
-  hipLaunchKernelGGL((k_sp_reduce<T, OP>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds, st, ds.win,
-                     ds.small, ds.big, c0, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0], root, bs);
+  const int nfo = (int)h.fo_chunks.size();
+  if constexpr (OP != OP_MAXLOC) {
+    if (atomic) {
+      const size_t lds_a = lds + (size_t)hs.maxbig * (ub + 8);
+      rc = allow_lds((const void *)&k_sp_reduce<T, OP, true>, lds_a);
+      if (rc) return rc;
+      hipLaunchKernelGGL((k_sp_reduce<T, OP, true>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds_a, st,
+                         ds.win, ds.small, ds.big, c0, d.fo_chunks, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0],
+                         root, bs, hs.cap * bs, nfo);
+      return sp_check();
+    }
+  }
+  rc = allow_lds((const void *)&k_sp_reduce<T, OP, false>, lds);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_sp_reduce<T, OP, false>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds, st, ds.win,
+                     ds.small, ds.big, c0, d.fo_chunks, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0], root, bs,
+                     hs.cap * bs, nfo);
   for (size_t k = 1; k < h.levels.size(); k++) {
     const int nch = (int)h.levels[k].chunks.size();
     hipLaunchKernelGGL((k_det_chunk<T, OP>), dim3((unsigned)((nch * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
@@ -409,7 +593,7 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st)
 }
 
 template <typename T>
-int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
+int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomic, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const int64_t L = sf->nleaves;
@@ -428,35 +612,49 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_
   const size_t lds = (size_t)hs.cap * ub;
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
-  if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, lds))) return rc;
-  if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, lds))) return rc;
-  hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.small, ds.big, d.fo_chunks,
-                     d.troot, d.toff, ds.lpos, scr, sums, root, bs);
-  if (nch) {
-    hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d.fo_root_first, nlarge,
-                       d.fo_chunks, sums, root, bs);
-    hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.big, d.fo_chunks,
-                       ds.lpos, scr, (const T *)sums, bs);
+  if (atomic || !std::is_integral<T>::value) {  // floating point: atomic only
+    const size_t lds_a = lds + (size_t)hs.maxbig * (ub + 8);
+    if ((rc = allow_lds((const void *)&k_sp_fop_atomic<T>, lds_a))) return rc;
+    hipLaunchKernelGGL((k_sp_fop_atomic<T>), dim3(gw), dim3(kStageThreads), lds_a, st, ds.win, ds.small, ds.big,
+                       d.fo_chunks, d.troot, d.toff, ds.lpos, scr, root, bs, hs.cap * bs, nch);
+    rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
+    if (rc) return rc;
+    return sp_check();
   }
-  rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
-  if (rc) return rc;
-  return sp_check();
+  if constexpr (std::is_integral<T>::value) {
+    if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, lds))) return rc;
+    if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, lds))) return rc;
+    hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.small, ds.big,
+                       d.fo_chunks, d.troot, d.toff, ds.lpos, scr, sums, root, bs);
+    if (nch) {
+      hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock),
+                         0, st, d.fo_root_first, nlarge, d.fo_chunks, sums, root, bs);
+      hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.big, d.fo_chunks,
+                         ds.lpos, scr, (const T *)sums, bs);
+    }
+    rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
+    if (rc) return rc;
+    return sp_check();
+  }
+  return SF_ERR_UNSUPPORTED;  // deterministic FetchAndOp is defined for integers only
 }
 
-template int launch_reduce_part<double, OP_SUM>(sf_s *, const double *, double *, int, hipStream_t);
-template int launch_reduce_part<double, OP_MAX>(sf_s *, const double *, double *, int, hipStream_t);
-template int launch_reduce_part<double, OP_MIN>(sf_s *, const double *, double *, int, hipStream_t);
-template int launch_reduce_part<float, OP_SUM>(sf_s *, const float *, float *, int, hipStream_t);
-template int launch_reduce_part<float, OP_MAX>(sf_s *, const float *, float *, int, hipStream_t);
-template int launch_reduce_part<float, OP_MIN>(sf_s *, const float *, float *, int, hipStream_t);
-template int launch_reduce_part<int32_t, OP_SUM>(sf_s *, const int32_t *, int32_t *, int, hipStream_t);
-template int launch_reduce_part<int32_t, OP_MAX>(sf_s *, const int32_t *, int32_t *, int, hipStream_t);
-template int launch_reduce_part<int32_t, OP_MIN>(sf_s *, const int32_t *, int32_t *, int, hipStream_t);
-template int launch_reduce_part<int64_t, OP_SUM>(sf_s *, const int64_t *, int64_t *, int, hipStream_t);
-template int launch_reduce_part<int64_t, OP_MAX>(sf_s *, const int64_t *, int64_t *, int, hipStream_t);
-template int launch_reduce_part<int64_t, OP_MIN>(sf_s *, const int64_t *, int64_t *, int, hipStream_t);
-template int launch_reduce_part<Pair, OP_MAXLOC>(sf_s *, const Pair *, Pair *, int, hipStream_t);
-template int launch_fop_part<int32_t>(sf_s *, int32_t *, const int32_t *, int32_t *, int, hipStream_t);
-template int launch_fop_part<int64_t>(sf_s *, int64_t *, const int64_t *, int64_t *, int, hipStream_t);
+template int launch_reduce_part<double, OP_SUM>(sf_s *, const double *, double *, int, bool, hipStream_t);
+template int launch_reduce_part<double, OP_MAX>(sf_s *, const double *, double *, int, bool, hipStream_t);
+template int launch_reduce_part<double, OP_MIN>(sf_s *, const double *, double *, int, bool, hipStream_t);
+template int launch_reduce_part<float, OP_SUM>(sf_s *, const float *, float *, int, bool, hipStream_t);
+template int launch_reduce_part<float, OP_MAX>(sf_s *, const float *, float *, int, bool, hipStream_t);
+template int launch_reduce_part<float, OP_MIN>(sf_s *, const float *, float *, int, bool, hipStream_t);
+template int launch_reduce_part<int32_t, OP_SUM>(sf_s *, const int32_t *, int32_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int32_t, OP_MAX>(sf_s *, const int32_t *, int32_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int32_t, OP_MIN>(sf_s *, const int32_t *, int32_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int64_t, OP_SUM>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int64_t, OP_MAX>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int64_t, OP_MIN>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
+template int launch_reduce_part<Pair, OP_MAXLOC>(sf_s *, const Pair *, Pair *, int, bool, hipStream_t);
+template int launch_fop_part<int32_t>(sf_s *, int32_t *, const int32_t *, int32_t *, int, bool, hipStream_t);
+template int launch_fop_part<int64_t>(sf_s *, int64_t *, const int64_t *, int64_t *, int, bool, hipStream_t);
+template int launch_fop_part<double>(sf_s *, double *, const double *, double *, int, bool, hipStream_t);
+template int launch_fop_part<float>(sf_s *, float *, const float *, float *, int, bool, hipStream_t);
 
 }  // namespace sfi

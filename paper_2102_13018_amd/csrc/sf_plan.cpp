@@ -134,6 +134,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     for (auto &x : small_in_win) sp.small.push_back(x.second);
     cur.small1 = (int32_t)sp.small.size();
     cur.big1 = (int32_t)sp.big.size();
+    sp.maxbig = std::max(sp.maxbig, cur.big1 - cur.big0);
     cur.n = (int32_t)cur_n;
     sp.win.push_back(cur);
     small_in_win.clear();

@@ -1,6 +1,6 @@
 """GPU parity at the full workload sizes, in the launch configuration the
-benchmark times (default setup options: the partitioned deterministic path
-for the large SFs, the tuned persistent atomic grids).  The C oracle handles
+benchmark times (default setup options: the partitioned path for the large
+SFs), plus the direct atomic kernels with partitioning switched off.  The C oracle handles
 these sizes in seconds, so outputs are compared element by element: bit-exact
 for REPLACE / MAX / MAXLOC / integer work / the deterministic sum, within the
 stated tolerance for the atomic FP sum."""
@@ -42,6 +42,32 @@ def run(sf, kind, a, b, op):
 @pytest.fixture(scope="module")
 def spmv():
     return inputs.spmv_ghost(seed=3)
+
+
+@pytest.mark.parametrize("part", ["auto", "off"])
+def test_spmv_ghost_full_atomic(spmv, part):
+    """Atomic mode at full size: partitioned (default) and the direct
+    persistent atomic kernels (partitioning off)."""
+    g = spmv
+    rng = np.random.default_rng(1005)
+    sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="atomic", partition=part)
+    root = rng.standard_normal(g.nroots)
+    leaf = rng.standard_normal(g.nleaves)
+    want = oracle.reduce(g.nroots, g.iroot, None, leaf, root, "sum")
+    ok, worst = atomic_sum_tolerance(run(sf, "reduce", leaf, root, "sum"), want, root, leaf, g.iroot, 1e-12)
+    assert ok, worst
+    same(run(sf, "reduce", leaf, root, "min"), oracle.reduce(g.nroots, g.iroot, None, leaf, root, "min"),
+         f"reduce min atomic ({part})")
+    l32, r32 = leaf.astype(np.float32), root.astype(np.float32)
+    w32 = oracle.reduce(g.nroots, g.iroot, None, l32, r32, "sum")
+    ok, worst = atomic_sum_tolerance(run(sf, "reduce", l32, r32, "sum"), w32, r32, l32, g.iroot, 1e-5)
+    assert ok, worst
+    r0 = rng.integers(0, 100, g.nroots).astype(np.int64)
+    lf = rng.integers(0, 100, g.nleaves).astype(np.int64)
+    r, l, u = dev(r0), dev(lf), dev(np.zeros(g.nleaves, np.int64))
+    sf.fetch_and_op(r, l, u, "sum", unit=S.SfUnit(S.SF_I64, 1))
+    torch.cuda.synchronize()
+    check_fetch_chain(g.iroot, np.arange(g.nleaves), r0, lf, host(u, lf), host(r, r0))
 
 
 def test_spmv_ghost_full(spmv):

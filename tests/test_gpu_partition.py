@@ -1,6 +1,8 @@
-"""GPU parity of the partitioned deterministic path (pass A into bucket-major
-scratch, pass B per window on its XCD): forced on at test sizes, it must give
-the oracle's bits exactly like the direct path."""
+"""GPU parity of the partitioned path (pass A into window-major scratch,
+pass B per window from LDS): forced on at test sizes, the deterministic mode
+must give the oracle's bits exactly like the direct path, and the atomic
+mode must meet the atomic bar (order-free results exact, FP sums within
+tolerance, FetchAndOp a valid prefix chain)."""
 import numpy as np
 import pytest
 
@@ -147,3 +149,120 @@ def test_partition_matches_direct_bitwise(zipf):
     a = run_reduce(g, leaf, root, "sum", "on")
     b = run_reduce(g, leaf, root, "sum", "off")
     assert same_bits(a, b)
+
+
+# ------------------------------------------------------------ atomic mode
+# With reduce_mode="atomic" the partitioned path keeps the per-window work of
+# the deterministic one, and the chunks of a large root meet at the root
+# through native atomics (reduce) or returning atomic adds (FetchAndOp).
+
+def run_reduce_mode(g, leaf, root, op, mode, part="on"):
+    sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup(reduce_mode=mode, partition=part)
+    from helpers import unit
+    l, r = dev(leaf), dev(root)
+    sf.reduce(l, r, op, unit=unit(root))
+    torch.cuda.synchronize()
+    return host(r, root)
+
+
+def run_fetch_mode(g, root, leaf, upd, mode, part="on"):
+    sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup(reduce_mode=mode, partition=part)
+    from helpers import unit
+    r, l, u = dev(root), dev(leaf), dev(upd)
+    sf.fetch_and_op(r, l, u, "sum", unit=unit(root))
+    torch.cuda.synchronize()
+    return host(r, root), host(u, upd)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.int32, np.int64])
+@pytest.mark.parametrize("op", ["sum", "max", "min"])
+def test_partition_atomic_reduce(zipf, dtype, op):
+    from helpers import atomic_sum_tolerance
+    g = zipf
+    rng = np.random.default_rng(810)
+    kind = "full" if np.dtype(dtype).kind == "i" else "normal"
+    leaf = inputs.unit_data(rng, g.leafspace, 1, dtype, kind)
+    root = inputs.unit_data(rng, g.nroots, 1, dtype, kind)
+    want = oracle.reduce(g.nroots, g.iroot, None, leaf, root, op)
+    got = run_reduce_mode(g, leaf, root, op, "atomic")
+    if op == "sum" and np.dtype(dtype).kind == "f":
+        rtol = 1e-12 if dtype == np.float64 else 1e-5
+        ok, worst = atomic_sum_tolerance(got, want, root, leaf, g.iroot, rtol)
+        assert ok, f"atomic partition sum {np.dtype(dtype)}: {worst:.3g}"
+        untouched = np.bincount(g.iroot, minlength=g.nroots) == 0
+        assert same_bits(got[untouched], root[untouched])
+    else:   # integer sums wrap in any order; MAX/MIN are order-free
+        check(got, want, f"atomic partition {op} {np.dtype(dtype)}")
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64, np.float64])
+def test_partition_atomic_fetch_chain(zipf, dtype):
+    """Integer-valued data (also in float64, where every partial sum is
+    exact): the fetched values of each root form a prefix chain and the
+    final roots are exact."""
+    from helpers import check_fetch_chain
+    g = zipf
+    rng = np.random.default_rng(811)
+    root0 = rng.integers(0, 100, g.nroots).astype(dtype)
+    leaf = rng.integers(0, 100, g.nleaves).astype(dtype)
+    r, u = run_fetch_mode(g, root0, leaf, np.zeros(g.nleaves, dtype), "atomic")
+    check_fetch_chain(g.iroot, np.arange(g.nleaves), root0, leaf, u, r)
+
+
+def test_partition_atomic_fetch_float(zipf):
+    from helpers import atomic_sum_tolerance
+    g = zipf
+    rng = np.random.default_rng(812)
+    root0 = rng.standard_normal(g.nroots)
+    leaf = np.abs(rng.standard_normal(g.nleaves))
+    r, u = run_fetch_mode(g, root0, leaf, np.zeros(g.nleaves), "atomic")
+    want = oracle.reduce(g.nroots, g.iroot, None, leaf, root0, "sum")
+    ok, worst = atomic_sum_tolerance(r, want, root0, leaf, g.iroot, 1e-12)
+    assert ok, worst
+    lo, hi = root0[g.iroot], r[g.iroot]
+    assert np.all(u >= lo - 1e-9 * np.abs(hi)) and np.all(u <= hi + 1e-9 * np.abs(hi))
+    # float32: same checks at its own tolerance
+    r32, u32 = run_fetch_mode(g, root0.astype(np.float32), leaf.astype(np.float32),
+                              np.zeros(g.nleaves, np.float32), "atomic")
+    want32 = oracle.reduce(g.nroots, g.iroot, None, leaf.astype(np.float32), root0.astype(np.float32), "sum")
+    ok, worst = atomic_sum_tolerance(r32, want32, root0.astype(np.float32), leaf.astype(np.float32), g.iroot, 1e-5)
+    assert ok, worst
+
+
+def test_partition_atomic_holes_and_units():
+    from helpers import atomic_sum_tolerance, check_fetch_chain
+    g = inputs.single_sf(seed=14, nroots=5000, nleaves=70001, leafspace=90001)
+    rng = np.random.default_rng(813)
+    leaf = rng.standard_normal((g.leafspace, 3))
+    root = rng.standard_normal((g.nroots, 3))
+    want = oracle.reduce(g.nroots, g.iroot, g.ilocal, leaf, root)
+    got = run_reduce_mode(g, leaf, root, "sum", "atomic")
+    slots = g.ilocal
+    ok, worst = atomic_sum_tolerance(got, want, root, leaf[slots], g.iroot, 1e-12)
+    assert ok, worst
+    li = inputs.unit_data(rng, g.leafspace, 5, np.int32, "full")
+    ri = inputs.unit_data(rng, g.nroots, 5, np.int32, "full")
+    check(run_reduce_mode(g, li, ri, "max", "atomic"), oracle.reduce(g.nroots, g.iroot, g.ilocal, li, ri, "max"),
+          "atomic max bs 5 with holes")
+    r0 = rng.integers(0, 100, g.nroots).astype(np.int64)
+    lf = rng.integers(0, 100, g.leafspace).astype(np.int64)
+    u0 = np.full(g.leafspace, -5, np.int64)
+    r, u = run_fetch_mode(g, r0, lf, u0, "atomic")
+    holes = np.ones(g.leafspace, bool)
+    holes[slots] = False
+    assert (u[holes] == -5).all(), "holes untouched"
+    check_fetch_chain(g.iroot, slots, r0, lf, u, r)
+
+
+def test_partition_atomic_single_root():
+    """Every leaf on one root: all chunks meet at one address."""
+    n = 200003
+    g1 = inputs.Graph(2, np.full(n, 1, np.int64), None, np.zeros(n, np.int64), n)
+    rng = np.random.default_rng(814)
+    leaf = rng.integers(-1000, 1000, n).astype(np.int64)
+    root = np.array([7, 11], np.int64)
+    check(run_reduce_mode(g1, leaf, root, "sum", "atomic"), oracle.reduce(2, g1.iroot, None, leaf, root), "one root")
+    from helpers import check_fetch_chain
+    ones = np.ones(n, np.int64)
+    r, u = run_fetch_mode(g1, root, ones, np.zeros(n, np.int64), "atomic")
+    check_fetch_chain(g1.iroot, np.arange(n), root, ones, u, r)
