@@ -69,6 +69,18 @@ struct DevChunk {  // one aligned chunk of a root's (sorted) value list
   int32_t pad;
 };
 
+struct DevSRoot {  // a whole root of a window of the partitioned path
+  int32_t root;     // its index
+  int32_t on;       // window-relative offset of its first sorted leaf | degree << 16
+};
+
+struct DevWChunk {  // a level-0 chunk of a large root, as placed in a window
+  int32_t onf;      // window-relative offset | (n - 1) << 16 | first-of-root << 24 | last-of-root << 25
+  int32_t dst;      // level-0 destination: >= 0 next-level slot; < 0 final, root = -dst-1
+  int32_t root;     // the chunk's root
+  int32_t k;        // level-0 chunk ordinal (FetchAndOp chunk sums)
+};
+
 // ------------------------------------------------------------- host plan
 struct Segment {
   int64_t rank;
@@ -111,7 +123,8 @@ struct HostPlan {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     int32_t maxbig = 0;               // most level-0 chunks in one window
     std::vector<DevSWin> win;
-    std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
+    std::vector<DevSRoot> sroot;      // whole roots, window-major (by degree class inside a window)
+    std::vector<DevWChunk> wchunk;    // chunks of large roots, window-major, in chunk order
     std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start
     std::vector<int32_t> pa_dst;      // [L] pass-A tile-major, increasing scratch slot in a tile
     std::vector<uint16_t> pa_loc;     // [L] tile-local processing offset of that leaf
@@ -136,7 +149,9 @@ struct DevPlan {
   int32_t *fo_root_first = nullptr;
   struct Stage {
     DevSWin *win = nullptr;
-    int32_t *small = nullptr, *big = nullptr, *pa_dst = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
+    DevSRoot *sroot = nullptr;
+    DevWChunk *wchunk = nullptr;
+    int32_t *pa_dst = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
     uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
 };

@@ -126,98 +126,114 @@ __device__ __forceinline__ T lds_tree(const T *lds, int o, int n, int bs, int c)
   return x[0];
 }
 
-// Root of level-0 chunk k and whether k is its root's first (bit 0) and
-// last (bit 1) chunk, for the per-window runs of the atomic mode.
-__device__ __forceinline__ void chunk_info(const DevChunk *__restrict__ fo, int k, int nfo, int32_t *cr,
-                                           int32_t *cf) {
-  const int32_t r = fo[k].dst;
-  const int32_t prev = k > 0 ? fo[k - 1].dst : -1;
-  const int32_t next = k + 1 < nfo ? fo[k + 1].dst : -1;
-  *cr = r;
-  *cf = (prev != r ? 1 : 0) | (next != r ? 2 : 0);
+// Window-relative offset and degree of a whole root; offset, length and
+// first / last-of-root flags of a chunk.
+__device__ __forceinline__ int sr_off(int32_t on) { return on & 0xffff; }
+__device__ __forceinline__ int sr_n(int32_t on) { return on >> 16; }
+__device__ __forceinline__ int wc_off(int32_t onf) { return onf & 0xffff; }
+__device__ __forceinline__ int wc_n(int32_t onf) { return ((onf >> 16) & 0xff) + 1; }
+__device__ __forceinline__ bool wc_first(int32_t onf) { return (onf >> 24) & 1; }
+__device__ __forceinline__ bool wc_last(int32_t onf) { return (onf >> 25) & 1; }
+
+// Pass-B blocks are bound by chains of dependent global loads rather than
+// by bandwidth, so every block first issues the loads that do not depend on
+// the window (its first whole roots' descriptors and root values, its chunk
+// descriptors), then loads the window; the LDS after the window's values
+// holds the chunk descriptors (byte offset cd_off) and per-chunk values
+// (byte offset cv_off).
+constexpr int kSmallU = 2;  // whole-root elements per thread in flight
+
+// Canonical pairwise tree of n <= kSmallMaxDeg sorted values.  Its lowest
+// three levels stay inside aligned blocks of 8 (a short last block keeps its
+// own tree), so it is evaluated as the trees of those blocks followed by the
+// tree of the (at most 4) block values -- a third of the registers of one
+// 32-wide tree.
+template <typename T, int OP>
+__device__ __forceinline__ T small_tree(const T *lds, int o, int n, int bs, int c) {
+  static_assert(kSmallMaxDeg <= 32, "two levels above blocks of 8");
+  if (n <= 1) return ld(lds + o * bs + c);
+  if (n <= 2) return lds_tree<T, OP, 2>(lds, o, n, bs, c);
+  if (n <= 4) return lds_tree<T, OP, 4>(lds, o, n, bs, c);
+  if (n <= 8) return lds_tree<T, OP, 8>(lds, o, n, bs, c);
+  const int nblk = (n + 7) >> 3;
+  T b[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (k < nblk) b[k] = lds_tree<T, OP, 8>(lds, o + 8 * k, min(8, n - 8 * k), bs, c);
+  if (nblk > 3) b[2] = Op<OP, T>::apply(b[2], b[3]);
+  b[0] = Op<OP, T>::apply(b[0], b[1]);
+  if (nblk > 2) b[0] = Op<OP, T>::apply(b[0], b[2]);
+  return b[0];
+}
+
+// The kSmallU whole-root elements q0 + u * kStageThreads of a window: their
+// descriptors and root values.
+template <typename T>
+__device__ __forceinline__ void small_fetch(const DevSRoot *__restrict__ sroot, const T *__restrict__ root,
+                                            const DevSWin &win, int q0, int nsmall, int bs, DevSRoot (&sd)[kSmallU],
+                                            T (&rv)[kSmallU]) {
+#pragma unroll
+  for (int u = 0; u < kSmallU; u++) {
+    const int q = q0 + u * kStageThreads;
+    if (q < nsmall) sd[u] = sroot[win.small0 + q / bs];
+  }
+#pragma unroll
+  for (int u = 0; u < kSmallU; u++) {
+    const int q = q0 + u * kStageThreads;
+    if (q < nsmall) rv[u] = ld(root + (int64_t)sd[u].root * bs + (q % bs));
+  }
 }
 
 // ------------------------------------------------------------- pass B reduce
-// ATOM: the chunk values of a root are combined per window (in chunk order,
-// in LDS after the window's values, at element offset ctot_off, followed by
-// each chunk's root and first/last flags); a root whose
-// chunks all lie in this window is then updated plainly, one that spans
-// windows through one native atomic per window, in arrival order, instead of
-// the chunk-level trees.  fo (nfo chunks) gives each chunk's root.
+// Whole roots: one thread per (root, element) evaluates its tree from LDS.
+// Chunks of large roots: one wavefront per chunk computes the chunk's tree
+// into LDS; then one thread per chunk writes it on -- to its root when the
+// chunk is the root's only one, else to the next chunk level (lvl_out).
+// ATOM: the chunks of a root that lie in this window are combined in chunk
+// order; a root whose chunks all lie in this window is then updated plainly,
+// one that spans windows through one native atomic per window, in arrival
+// order, in place of the chunk-level trees.
 template <typename T, int OP, bool ATOM>
-__global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__restrict__ wins,
-                                                             const int32_t *__restrict__ small,
-                                                             const int32_t *__restrict__ big,
-                                                             const DevChunk *__restrict__ chunks0,
-                                                             const DevChunk *__restrict__ fo,
-                                                             const int32_t *__restrict__ troot,
-                                                             const int32_t *__restrict__ toff,
-                                                             const uint16_t *__restrict__ lpos,
-                                                             const T *__restrict__ scr, T *__restrict__ lvl_out,
-                                                             T *__restrict__ root, int bs, int ctot_off, int nfo) {
+__device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot,
+                                               const DevWChunk *__restrict__ wchunk,
+                                               const uint16_t *__restrict__ lpos, const T *__restrict__ scr,
+                                               T *__restrict__ lvl_out, T *__restrict__ root, int bs, int cd_off,
+                                               int cv_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
+  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
+  T *cv = reinterpret_cast<T *>(smem + cv_off);
   const DevSWin win = wins[blockIdx.x];
+  const int nsmall = (win.small1 - win.small0) * bs;
+  const int nb = win.big1 - win.big0;
+  DevSRoot sd[kSmallU];
+  T rv[kSmallU];
+  small_fetch(sroot, root, win, threadIdx.x, nsmall, bs, sd, rv);
+  for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
   win_load(lds, scr, lpos, win, bs);
   __syncthreads();
-  // whole roots of degree <= kSmallMaxDeg: one thread per (root, element),
-  // U of them at a time so that their dependent index and root loads overlap
-  const int nsmall = (win.small1 - win.small0) * bs;
-  constexpr int U = 4;
-  for (int q0 = threadIdx.x; q0 < nsmall; q0 += kStageThreads * U) {
-    int t[U], o[U], n[U];
-    int64_t rp[U];
-    T rv[U];
+  for (int q0 = threadIdx.x;;) {
 #pragma unroll
-    for (int u = 0; u < U; u++) {
+    for (int u = 0; u < kSmallU; u++) {
       const int q = q0 + u * kStageThreads;
-      n[u] = 0;
-      if (q < nsmall) {
-        const int k = q / bs;
-        t[u] = small[win.small0 + k];
-        rp[u] = q - k * bs;  // element, completed below
-      }
+      if (q >= nsmall) continue;
+      const int c = q % bs;
+      const T v = small_tree<T, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
+      st(root + (int64_t)sd[u].root * bs + c, Op<OP, T>::apply(rv[u], v));
+      __builtin_amdgcn_sched_barrier(0);  // one tree's registers at a time
     }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      if (q0 + u * kStageThreads < nsmall) {
-        const int g0 = toff[t[u]];
-        n[u] = toff[t[u] + 1] - g0;
-        o[u] = g0 - win.g0;
-        rp[u] += (int64_t)troot[t[u]] * bs;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (n[u] > 0) rv[u] = ld(root + rp[u]);
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      if (n[u] == 0) continue;
-      const int c = (int)(rp[u] % bs);
-      T v;
-      if (n[u] <= 1)
-        v = lds_tree<T, OP, 1>(lds, o[u], n[u], bs, c);
-      else if (n[u] <= 2)
-        v = lds_tree<T, OP, 2>(lds, o[u], n[u], bs, c);
-      else if (n[u] <= 4)
-        v = lds_tree<T, OP, 4>(lds, o[u], n[u], bs, c);
-      else if (n[u] <= 8)
-        v = lds_tree<T, OP, 8>(lds, o[u], n[u], bs, c);
-      else if (n[u] <= 16)
-        v = lds_tree<T, OP, 16>(lds, o[u], n[u], bs, c);
-      else
-        v = lds_tree<T, OP, 32>(lds, o[u], n[u], bs, c);
-      st(root + rp[u], Op<OP, T>::apply(rv[u], v));
-    }
+    q0 += kSmallU * kStageThreads;
+    if (q0 >= nsmall) break;
+    small_fetch(sroot, root, win, q0, nsmall, bs, sd, rv);
   }
-  // aligned chunks of larger roots: one wavefront per chunk, kChunkLPT per lane
+  if (nb == 0) return;
   constexpr int LPT = kChunkLPT;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
-    const int k = big[ci];
-    const DevChunk ch = chunks0[k];
-    const int o = ch.src - win.g0 + lane * LPT;
-    const int m = ch.n - lane * LPT;
+  for (int j = wv; j < nb; j += kStageThreads / 64) {
+    const int32_t onf = cd[j].onf;
+    const int n = wc_n(onf);
+    const int o = wc_off(onf) + lane * LPT;
+    const int m = n - lane * LPT;
     for (int c = 0; c < bs; c++) {
       T x[LPT];
 #pragma unroll
@@ -232,242 +248,135 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_reduce(const DevSWin *__re
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
         const T o2 = shfl_down(v, d);
-        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < ch.n) v = Op<OP, T>::apply(v, o2);
+        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < n) v = Op<OP, T>::apply(v, o2);
       }
-      if (lane == 0) {
-        if constexpr (ATOM) {
-          lds[ctot_off + (ci - win.big0) * bs + c] = v;
-          if (c == 0) {
-            int32_t *cr = reinterpret_cast<int32_t *>(lds + ctot_off + (win.big1 - win.big0) * bs);
-            chunk_info(fo, k, nfo, cr + (ci - win.big0), cr + (win.big1 - win.big0) + (ci - win.big0));
-          }
-        } else if (ch.dst < 0) {
-          T *rp = root + (int64_t)(-ch.dst - 1) * bs + c;
-          st(rp, Op<OP, T>::apply(ld(rp), v));
-        } else {
-          st(lvl_out + (int64_t)ch.dst * bs + c, v);
-        }
-      }
+      if (lane == 0) st(cv + j * bs + c, v);
     }
   }
-  if constexpr (ATOM) {
-    __syncthreads();
-    const T *ctot = lds + ctot_off;
-    const int nb = win.big1 - win.big0;
-    const int32_t *cr = reinterpret_cast<const int32_t *>(ctot + nb * bs);
-    const int32_t *cf = cr + nb;
-    for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
-      const int j = q / bs, c = q - j * bs;
-      const int32_t r = cr[j];
-      if (j > 0 && cr[j - 1] == r) continue;  // not the first chunk of its run
-      T acc = ctot[j * bs + c];
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+    const int j = q / bs, c = q - j * bs;
+    if constexpr (ATOM) {
+      const int32_t r = cd[j].root;
+      if (j > 0 && cd[j - 1].root == r) continue;  // not the first chunk of its run
+      T acc = ld(cv + q);
       int j1 = j + 1;
-      for (; j1 < nb && cr[j1] == r; j1++) acc = Op<OP, T>::apply(acc, ctot[j1 * bs + c]);
-      const bool whole = (cf[j] & 1) && (cf[j1 - 1] & 2);
+      for (; j1 < nb && cd[j1].root == r; j1++) acc = Op<OP, T>::apply(acc, ld(cv + j1 * bs + c));
       T *rp = root + (int64_t)r * bs + c;
-      if (whole)
+      if (wc_first(cd[j].onf) && wc_last(cd[j1 - 1].onf))
         st(rp, Op<OP, T>::apply(ld(rp), acc));
       else
         AtomicG<OP, T>::run(rp, acc);
+    } else {
+      const int32_t dst = cd[j].dst;
+      if (dst < 0) {
+        T *rp = root + (int64_t)(-dst - 1) * bs + c;
+        st(rp, Op<OP, T>::apply(ld(rp), ld(cv + q)));
+      } else {
+        st(lvl_out + (int64_t)dst * bs + c, ld(cv + q));
+      }
     }
   }
 }
+
+// Windows of units up to 8 bytes take 64 KB of LDS, so two blocks share a CU
+// when the kernel stays within 64 VGPRs (8 waves per SIMD); wider units
+// leave room for one block per CU.
+#define SP_REDUCE_ARGS                                                                                             \
+  const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot, const DevWChunk *__restrict__ wchunk,     \
+      const uint16_t *__restrict__ lpos, const T *__restrict__ scr, T *__restrict__ lvl_out, T *__restrict__ root, \
+      int bs, int cd_off, int cv_off
+template <typename T, int OP, bool ATOM>
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sp_reduce2(SP_REDUCE_ARGS) {
+  sp_reduce_body<T, OP, ATOM>(wins, sroot, wchunk, lpos, scr, lvl_out, root, bs, cd_off, cv_off);
+}
+template <typename T, int OP, bool ATOM>
+__global__ __launch_bounds__(kStageThreads) void k_sp_reduce(SP_REDUCE_ARGS) {
+  sp_reduce_body<T, OP, ATOM>(wins, sroot, wchunk, lpos, scr, lvl_out, root, bs, cd_off, cv_off);
+}
+#undef SP_REDUCE_ARGS
 
 // ------------------------------------------------------- pass B FetchAndOp
-// B1: small roots scan sequentially in leaf order (fetched values replace
-// the leaf values in the window); chunks of large roots write their sums.
+// Whole roots (all kernels below): one thread per (root, element) scans the
+// root's leaves sequentially in leaf order; the fetched values replace the
+// leaf values in the window.
+template <typename T>
+__device__ __forceinline__ void small_scan(T *lds, const DevSRoot *__restrict__ sroot, T *__restrict__ root,
+                                           const DevSWin &win, int nsmall, int bs, DevSRoot (&sd)[kSmallU],
+                                           T (&rv)[kSmallU]) {
+  for (int q0 = threadIdx.x;;) {
+#pragma unroll
+    for (int u = 0; u < kSmallU; u++) {
+      const int q = q0 + u * kStageThreads;
+      if (q >= nsmall) continue;
+      const int c = q % bs;
+      const int o0 = sr_off(sd[u].on), o1 = o0 + sr_n(sd[u].on);
+      T a = rv[u];
+      for (int o = o0; o < o1; o++) {
+        T *e = lds + o * bs + c;
+        const T v = *e;
+        *e = a;
+        a = Op<OP_SUM, T>::apply(a, v);
+      }
+      root[(int64_t)sd[u].root * bs + c] = a;
+    }
+    q0 += kSmallU * kStageThreads;
+    if (q0 >= nsmall) break;
+    small_fetch(sroot, (const T *)root, win, q0, nsmall, bs, sd, rv);
+  }
+}
+
+// B1: whole roots as above; chunks of large roots write their sums.
 template <typename T>
 __global__ __launch_bounds__(kStageThreads) void k_sp_fop_b1(const DevSWin *__restrict__ wins,
-                                                             const int32_t *__restrict__ small,
-                                                             const int32_t *__restrict__ big,
-                                                             const DevChunk *__restrict__ fo_chunks,
-                                                             const int32_t *__restrict__ troot,
-                                                             const int32_t *__restrict__ toff,
+                                                             const DevSRoot *__restrict__ sroot,
+                                                             const DevWChunk *__restrict__ wchunk,
                                                              const uint16_t *__restrict__ lpos, T *__restrict__ scr,
-                                                             T *__restrict__ sums, T *__restrict__ root, int bs) {
+                                                             T *__restrict__ sums, T *__restrict__ root, int bs,
+                                                             int cd_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
+  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
   const DevSWin win = wins[blockIdx.x];
-  win_load(lds, scr, lpos, win, bs);
-  __syncthreads();
   const int nsmall = (win.small1 - win.small0) * bs;
-  for (int q = threadIdx.x; q < nsmall; q += kStageThreads) {
-    const int k = q / bs, c = q - (q / bs) * bs;
-    const int t = small[win.small0 + k];
-    const int o0 = toff[t] - win.g0, o1 = toff[t + 1] - win.g0;
-    T *rp = root + (int64_t)troot[t] * bs + c;
-    T a = *rp;
-    for (int o = o0; o < o1; o++) {
-      T *e = lds + o * bs + c;
-      const T v = *e;
-      *e = a;
-      a = Op<OP_SUM, T>::apply(a, v);
-    }
-    *rp = a;
-  }
-  constexpr int LPT = kChunkLPT;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
-    const int k = big[ci];
-    const DevChunk ch = fo_chunks[k];
-    const int o = ch.src - win.g0 + lane * LPT;
-    for (int c = 0; c < bs; c++) {
-      T a = T(0);
-#pragma unroll
-      for (int s = 0; s < LPT; s++)
-        if (lane * LPT + s < ch.n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
-#pragma unroll
-      for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
-      if (lane == 0) sums[(int64_t)k * bs + c] = a;
-    }
-  }
-  __syncthreads();
-  if (win.small1 > win.small0) win_store(lds, scr, lpos, win, bs);
-}
-
-// B3: chunks of large roots: exclusive prefix inside the chunk plus the
-// chunk's base (from the root scan), in the window, written back.
-template <typename T>
-__global__ __launch_bounds__(kStageThreads) void k_sp_fop_b3(const DevSWin *__restrict__ wins,
-                                                             const int32_t *__restrict__ big,
-                                                             const DevChunk *__restrict__ fo_chunks,
-                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
-                                                             const T *__restrict__ sums, int bs) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *lds = reinterpret_cast<T *>(smem);
-  const DevSWin win = wins[blockIdx.x];
-  if (win.big1 == win.big0) return;
-  win_load(lds, scr, lpos, win, bs);
-  __syncthreads();
-  constexpr int LPT = kChunkLPT;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int ci = win.big0 + wv; ci < win.big1; ci += kStageThreads / 64) {
-    const int k = big[ci];
-    const DevChunk ch = fo_chunks[k];
-    const int o = ch.src - win.g0 + lane * LPT;
-    const int m = ch.n - lane * LPT;
-    for (int c = 0; c < bs; c++) {
-      T x[LPT];
-      T lane_sum = T(0);
-#pragma unroll
-      for (int s = 0; s < LPT; s++) {
-        x[s] = s < m ? lds[(o + s) * bs + c] : T(0);
-        lane_sum = Op<OP_SUM, T>::apply(lane_sum, x[s]);
-      }
-      T inc = lane_sum;
-#pragma unroll
-      for (int d = 1; d < 64; d *= 2) {
-        const T o2 = shfl_up(inc, d);
-        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o2);
-      }
-      T a = Op<OP_SUM, T>::apply(sums[(int64_t)k * bs + c], wrap_sub(inc, lane_sum));
-#pragma unroll
-      for (int s = 0; s < LPT; s++) {
-        if (s < m) lds[(o + s) * bs + c] = a;
-        a = Op<OP_SUM, T>::apply(a, x[s]);
-      }
-    }
-  }
-  __syncthreads();
-  win_store(lds, scr, lpos, win, bs);
-}
-
-// ------------------------------------------------- pass B FetchAndOp, atomic
-// One pass: small roots scan in leaf order as in B1.  The chunks of a large
-// root that lie in this window form a run: their totals (in LDS after the
-// window's values, at element offset ctot_off, followed by each chunk's root
-// and first/last flags) give every chunk its offset
-// inside the run, and the run takes its base from the root -- plainly when
-// the run is the whole root, else with one native returning atomic add, so
-// the windows of a spanning root are applied in arrival order while the
-// leaves inside a window keep leaf order.
-template <typename T>
-__global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *__restrict__ wins,
-                                                                 const int32_t *__restrict__ small,
-                                                                 const int32_t *__restrict__ big,
-                                                                 const DevChunk *__restrict__ fo_chunks,
-                                                                 const int32_t *__restrict__ troot,
-                                                                 const int32_t *__restrict__ toff,
-                                                                 const uint16_t *__restrict__ lpos,
-                                                                 T *__restrict__ scr, T *__restrict__ root, int bs,
-                                                                 int ctot_off, int nfo) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *lds = reinterpret_cast<T *>(smem);
-  T *ctot = lds + ctot_off;
-  const DevSWin win = wins[blockIdx.x];
-  win_load(lds, scr, lpos, win, bs);
-  __syncthreads();
-  const int nsmall = (win.small1 - win.small0) * bs;
-  for (int q = threadIdx.x; q < nsmall; q += kStageThreads) {
-    const int k = q / bs, c = q - (q / bs) * bs;
-    const int t = small[win.small0 + k];
-    const int o0 = toff[t] - win.g0, o1 = toff[t + 1] - win.g0;
-    T *rp = root + (int64_t)troot[t] * bs + c;
-    T a = *rp;
-    for (int o = o0; o < o1; o++) {
-      T *e = lds + o * bs + c;
-      const T v = *e;
-      *e = a;
-      a = Op<OP_SUM, T>::apply(a, v);
-    }
-    *rp = a;
-  }
   const int nb = win.big1 - win.big0;
-  if (nb == 0) {
-    __syncthreads();
-    win_store(lds, scr, lpos, win, bs);
-    return;
-  }
+  DevSRoot sd[kSmallU];
+  T rv[kSmallU];
+  small_fetch(sroot, (const T *)root, win, threadIdx.x, nsmall, bs, sd, rv);
+  for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
+  win_load(lds, scr, lpos, win, bs);
+  __syncthreads();
+  if (nsmall > 0) small_scan(lds, sroot, root, win, nsmall, bs, sd, rv);
   constexpr int LPT = kChunkLPT;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t *cr = reinterpret_cast<int32_t *>(ctot + nb * bs);
-  int32_t *cf = cr + nb;
-  // 1: chunk totals
   for (int j = wv; j < nb; j += kStageThreads / 64) {
-    const int kk = big[win.big0 + j];
-    const DevChunk ch = fo_chunks[kk];
-    if (lane == 0) chunk_info(fo_chunks, kk, nfo, cr + j, cf + j);
-    const int o = ch.src - win.g0 + lane * LPT;
+    const DevWChunk ch = cd[j];
+    const int n = wc_n(ch.onf);
+    const int o = wc_off(ch.onf) + lane * LPT;
     for (int c = 0; c < bs; c++) {
       T a = T(0);
 #pragma unroll
       for (int s = 0; s < LPT; s++)
-        if (lane * LPT + s < ch.n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
+        if (lane * LPT + s < n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
 #pragma unroll
       for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
-      if (lane == 0) ctot[j * bs + c] = a;
+      if (lane == 0) sums[(int64_t)ch.k * bs + c] = a;
     }
   }
   __syncthreads();
-  // 2: per run, chunk offsets inside the run and the run's base from the root
-  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
-    const int j = q / bs, c = q - j * bs;
-    const int32_t r = cr[j];
-    if (j > 0 && cr[j - 1] == r) continue;  // not the first chunk of its run
-    int j1 = j;
-    T run = T(0);
-    for (; j1 < nb && cr[j1] == r; j1++) {
-      const T t = ctot[j1 * bs + c];
-      ctot[j1 * bs + c] = run;
-      run = Op<OP_SUM, T>::apply(run, t);
-    }
-    const bool whole = (cf[j] & 1) && (cf[j1 - 1] & 2);
-    T *rp = root + (int64_t)r * bs + c;
-    T base;
-    if (whole) {
-      base = *rp;
-      *rp = Op<OP_SUM, T>::apply(base, run);
-    } else {
-      base = fetch_add_g(rp, run);
-    }
-    for (int jj = j; jj < j1; jj++) ctot[jj * bs + c] = Op<OP_SUM, T>::apply(base, ctot[jj * bs + c]);
-  }
-  __syncthreads();
-  // 3: exclusive prefix inside each chunk plus the chunk's base
+  if (nsmall > 0) win_store(lds, scr, lpos, win, bs);
+}
+
+// Exclusive prefix inside chunk j of the window plus the chunk's base
+// (from LDS), written over the chunk's values.
+template <typename T>
+__device__ __forceinline__ void chunk_apply(T *lds, const DevWChunk *cd, const T *base, int nb, int bs) {
+  constexpr int LPT = kChunkLPT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = wv; j < nb; j += kStageThreads / 64) {
-    const DevChunk ch = fo_chunks[big[win.big0 + j]];
-    const int o = ch.src - win.g0 + lane * LPT;
-    const int m = ch.n - lane * LPT;
+    const int32_t onf = cd[j].onf;
+    const int o = wc_off(onf) + lane * LPT;
+    const int m = wc_n(onf) - lane * LPT;
     for (int c = 0; c < bs; c++) {
       T x[LPT];
       T lane_sum = T(0);
@@ -484,13 +393,115 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *
       }
       T excl = shfl_up(inc, 1);
       if (lane == 0) excl = T(0);
-      T a = Op<OP_SUM, T>::apply(ctot[j * bs + c], excl);
+      T a = Op<OP_SUM, T>::apply(base[j * bs + c], excl);
 #pragma unroll
       for (int s = 0; s < LPT; s++) {
         if (s < m) lds[(o + s) * bs + c] = a;
         a = Op<OP_SUM, T>::apply(a, x[s]);
       }
     }
+  }
+}
+
+// B3: chunks of large roots take their base from the root scan.
+template <typename T>
+__global__ __launch_bounds__(kStageThreads) void k_sp_fop_b3(const DevSWin *__restrict__ wins,
+                                                             const DevWChunk *__restrict__ wchunk,
+                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
+                                                             const T *__restrict__ sums, int bs, int cd_off,
+                                                             int cv_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *lds = reinterpret_cast<T *>(smem);
+  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
+  T *cv = reinterpret_cast<T *>(smem + cv_off);
+  const DevSWin win = wins[blockIdx.x];
+  const int nb = win.big1 - win.big0;
+  if (nb == 0) return;
+  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+    const int j = q / bs, c = q - j * bs;
+    const DevWChunk d = wchunk[win.big0 + j];
+    if (c == 0) cd[j] = d;
+    cv[q] = sums[(int64_t)d.k * bs + c];
+  }
+  win_load(lds, scr, lpos, win, bs);
+  __syncthreads();
+  chunk_apply(lds, cd, cv, nb, bs);
+  __syncthreads();
+  win_store(lds, scr, lpos, win, bs);
+}
+
+// ------------------------------------------------- pass B FetchAndOp, atomic
+// One pass: whole roots as in B1.  The chunks of a large root that lie in
+// this window form a run: their totals give every chunk its offset inside
+// the run, and the run takes its base from the root -- plainly when the run
+// is the whole root, else with one native returning atomic add, so the
+// windows of a spanning root are applied in arrival order while the leaves
+// inside a window keep leaf order.
+template <typename T>
+__global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *__restrict__ wins,
+                                                                 const DevSRoot *__restrict__ sroot,
+                                                                 const DevWChunk *__restrict__ wchunk,
+                                                                 const uint16_t *__restrict__ lpos,
+                                                                 T *__restrict__ scr, T *__restrict__ root, int bs,
+                                                                 int cd_off, int cv_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *lds = reinterpret_cast<T *>(smem);
+  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
+  T *cv = reinterpret_cast<T *>(smem + cv_off);
+  const DevSWin win = wins[blockIdx.x];
+  const int nsmall = (win.small1 - win.small0) * bs;
+  const int nb = win.big1 - win.big0;
+  DevSRoot sd[kSmallU];
+  T rv[kSmallU];
+  small_fetch(sroot, (const T *)root, win, threadIdx.x, nsmall, bs, sd, rv);
+  for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
+  win_load(lds, scr, lpos, win, bs);
+  __syncthreads();
+  if (nsmall > 0) small_scan(lds, sroot, root, win, nsmall, bs, sd, rv);
+  if (nb > 0) {
+    constexpr int LPT = kChunkLPT;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // 1: chunk totals
+    for (int j = wv; j < nb; j += kStageThreads / 64) {
+      const int32_t onf = cd[j].onf;
+      const int n = wc_n(onf);
+      const int o = wc_off(onf) + lane * LPT;
+      for (int c = 0; c < bs; c++) {
+        T a = T(0);
+#pragma unroll
+        for (int s = 0; s < LPT; s++)
+          if (lane * LPT + s < n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
+#pragma unroll
+        for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
+        if (lane == 0) cv[j * bs + c] = a;
+      }
+    }
+    __syncthreads();
+    // 2: per run, chunk offsets inside the run and the run's base from the root
+    for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+      const int j = q / bs, c = q - j * bs;
+      const int32_t r = cd[j].root;
+      if (j > 0 && cd[j - 1].root == r) continue;  // not the first chunk of its run
+      int j1 = j;
+      T run = T(0);
+      for (; j1 < nb && cd[j1].root == r; j1++) {
+        const T t = cv[j1 * bs + c];
+        cv[j1 * bs + c] = run;
+        run = Op<OP_SUM, T>::apply(run, t);
+      }
+      T *rp = root + (int64_t)r * bs + c;
+      T base;
+      if (wc_first(cd[j].onf) && wc_last(cd[j1 - 1].onf)) {
+        base = *rp;
+        *rp = Op<OP_SUM, T>::apply(base, run);
+      } else {
+        base = fetch_add_g(rp, run);
+      }
+      for (int jj = j; jj < j1; jj++) cv[jj * bs + c] = Op<OP_SUM, T>::apply(base, cv[jj * bs + c]);
+    }
+    __syncthreads();
+    // 3: exclusive prefix inside each chunk plus the chunk's base
+    chunk_apply(lds, cd, cv, nb, bs);
   }
   __syncthreads();
   win_store(lds, scr, lpos, win, bs);
@@ -548,6 +559,38 @@ static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_
                   : sp_move_w<uint32_t, 1>(sf, cls, leaf, scratch, (int)(ub / 4), st);
 }
 
+// LDS of a pass-B block: the window's values (cap units), then the chunk
+// descriptors and one value per chunk (at most maxbig chunks per window).
+struct PassBLds {
+  int cd_off, cv_off;
+  size_t bytes;
+};
+static PassBLds passb_lds(const HostPlan::Stage &hs, size_t ub) {
+  const size_t cd = ((size_t)hs.cap * ub + 15) / 16 * 16;
+  const size_t cv = cd + (size_t)hs.maxbig * sizeof(DevWChunk);
+  return {(int)cd, (int)cv, cv + (size_t)hs.maxbig * ub};
+}
+
+template <typename T, int OP, bool ATOM>
+static int sp_reduce_launch(unsigned gw, const PassBLds &pl, int cls, hipStream_t st, const DevSWin *win,
+                            const DevSRoot *sroot, const DevWChunk *wchunk, const uint16_t *lpos, const T *scr,
+                            T *lvl_out, T *root, int bs) {
+  if constexpr (sizeof(T) <= 8) {
+    if (cls == 0) {
+      int rc = allow_lds((const void *)&k_sp_reduce2<T, OP, ATOM>, pl.bytes);
+      if (rc) return rc;
+      hipLaunchKernelGGL((k_sp_reduce2<T, OP, ATOM>), dim3(gw), dim3(kStageThreads), pl.bytes, st, win, sroot, wchunk,
+                         lpos, scr, lvl_out, root, bs, pl.cd_off, pl.cv_off);
+      return SF_OK;
+    }
+  }
+  int rc = allow_lds((const void *)&k_sp_reduce<T, OP, ATOM>, pl.bytes);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_sp_reduce<T, OP, ATOM>), dim3(gw), dim3(kStageThreads), pl.bytes, st, win, sroot, wchunk, lpos,
+                     scr, lvl_out, root, bs, pl.cd_off, pl.cv_off);
+  return SF_OK;
+}
+
 template <typename T, int OP>
 int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hipStream_t st) {
   const DevPlan &d = sf->dp;
@@ -565,25 +608,19 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   T *buf[2] = {(T *)((char *)sf->scratch + main_bytes), (T *)((char *)sf->scratch + main_bytes + lvl)};
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
-  const size_t lds = (size_t)hs.cap * ub;
-  const DevChunk *c0 = h.levels.empty() ? nullptr : d.levels[0];
-  const int nfo = (int)h.fo_chunks.size();
+  const PassBLds pl = passb_lds(hs, ub);
+  const unsigned gw = (unsigned)hs.win.size();
   if constexpr (OP != OP_MAXLOC) {
     if (atomic) {
-      const size_t lds_a = lds + (size_t)hs.maxbig * (ub + 8);
-      rc = allow_lds((const void *)&k_sp_reduce<T, OP, true>, lds_a);
+      rc = sp_reduce_launch<T, OP, true>(gw, pl, cls, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr,
+                                         buf[0], root, bs);
       if (rc) return rc;
-      hipLaunchKernelGGL((k_sp_reduce<T, OP, true>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds_a, st,
-                         ds.win, ds.small, ds.big, c0, d.fo_chunks, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0],
-                         root, bs, hs.cap * bs, nfo);
       return sp_check();
     }
   }
-  rc = allow_lds((const void *)&k_sp_reduce<T, OP, false>, lds);
+  rc = sp_reduce_launch<T, OP, false>(gw, pl, cls, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr, buf[0],
+                                      root, bs);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_sp_reduce<T, OP, false>), dim3((unsigned)hs.win.size()), dim3(kStageThreads), lds, st, ds.win,
-                     ds.small, ds.big, c0, d.fo_chunks, d.troot, d.toff, ds.lpos, (const T *)scr, buf[0], root, bs,
-                     hs.cap * bs, nfo);
   for (size_t k = 1; k < h.levels.size(); k++) {
     const int nch = (int)h.levels[k].chunks.size();
     hipLaunchKernelGGL((k_det_chunk<T, OP>), dim3((unsigned)((nch * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
@@ -609,28 +646,27 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
   T *scr = (T *)sf->scratch;
   T *sums = (T *)((char *)sf->scratch + main_bytes);
   const unsigned gw = (unsigned)hs.win.size();
-  const size_t lds = (size_t)hs.cap * ub;
+  const PassBLds pl = passb_lds(hs, ub);
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   if (atomic || !std::is_integral<T>::value) {  // floating point: atomic only
-    const size_t lds_a = lds + (size_t)hs.maxbig * (ub + 8);
-    if ((rc = allow_lds((const void *)&k_sp_fop_atomic<T>, lds_a))) return rc;
-    hipLaunchKernelGGL((k_sp_fop_atomic<T>), dim3(gw), dim3(kStageThreads), lds_a, st, ds.win, ds.small, ds.big,
-                       d.fo_chunks, d.troot, d.toff, ds.lpos, scr, root, bs, hs.cap * bs, nch);
+    if ((rc = allow_lds((const void *)&k_sp_fop_atomic<T>, pl.bytes))) return rc;
+    hipLaunchKernelGGL((k_sp_fop_atomic<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
+                       ds.wchunk, ds.lpos, scr, root, bs, pl.cd_off, pl.cv_off);
     rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
     if (rc) return rc;
     return sp_check();
   }
   if constexpr (std::is_integral<T>::value) {
-    if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, lds))) return rc;
-    if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, lds))) return rc;
-    hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.small, ds.big,
-                       d.fo_chunks, d.troot, d.toff, ds.lpos, scr, sums, root, bs);
+    if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, pl.bytes))) return rc;
+    if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, pl.bytes))) return rc;
+    hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot, ds.wchunk,
+                       ds.lpos, scr, sums, root, bs, pl.cd_off);
     if (nch) {
       hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock),
                          0, st, d.fo_root_first, nlarge, d.fo_chunks, sums, root, bs);
-      hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), lds, st, ds.win, ds.big, d.fo_chunks,
-                         ds.lpos, scr, (const T *)sums, bs);
+      hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.wchunk, ds.lpos,
+                         scr, (const T *)sums, bs, pl.cd_off, pl.cv_off);
     }
     rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
     if (rc) return rc;

@@ -122,6 +122,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   sp.ta = ta;
   sp.cap = cap;
   std::vector<int32_t> win_g(L);  // window of the g-th sorted leaf
+  std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
   DevSWin cur{};
   int64_t cur_n = 0;
   std::vector<std::pair<int32_t, int32_t>> small_in_win;  // (class, t)
@@ -130,16 +131,16 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
                      [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
                        return x.first < y.first;
                      });
-    cur.small0 = (int32_t)sp.small.size();
-    for (auto &x : small_in_win) sp.small.push_back(x.second);
-    cur.small1 = (int32_t)sp.small.size();
-    cur.big1 = (int32_t)sp.big.size();
+    cur.small0 = (int32_t)small.size();
+    for (auto &x : small_in_win) small.push_back(x.second);
+    cur.small1 = (int32_t)small.size();
+    cur.big1 = (int32_t)big.size();
     sp.maxbig = std::max(sp.maxbig, cur.big1 - cur.big0);
     cur.n = (int32_t)cur_n;
     sp.win.push_back(cur);
     small_in_win.clear();
     cur = DevSWin{};
-    cur.big0 = (int32_t)sp.big.size();
+    cur.big0 = (int32_t)big.size();
     cur_n = 0;
   };
   static const std::vector<DevChunk> none;
@@ -159,7 +160,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
       while (left > 0) {
         const DevChunk &ch = lv0[chunk];
         if (cur_n + ch.n > cap) close_window();
-        sp.big.push_back(chunk);
+        big.push_back(chunk);
         for (int32_t g = ch.src; g < ch.src + ch.n; g++) win_g[g] = (int32_t)sp.win.size();
         cur_n += ch.n;
         left -= ch.n;
@@ -176,6 +177,28 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     base += sp.win[w].n;
   }
   if (base != L || chunk != (int32_t)lv0.size() || lv0.size() != hp.fo_chunks.size()) return SF_ERR_ARG;
+  // per-window descriptors: offsets relative to the window's first sorted leaf
+  const int64_t nfo = (int64_t)hp.fo_chunks.size();
+  for (int64_t w = 0; w < W; w++) {
+    const DevSWin &win = sp.win[w];
+    for (int32_t i = win.small0; i < win.small1; i++) {
+      const int32_t t = small[i];
+      const int64_t o = hp.toff[t] - win.g0, n = hp.toff[t + 1] - hp.toff[t];
+      if (o < 0 || o + n > win.n || o > 0xffff || n > kSmallMaxDeg) return SF_ERR_ARG;
+      sp.sroot.push_back({hp.troot[t], (int32_t)(o | (n << 16))});
+    }
+    for (int32_t i = win.big0; i < win.big1; i++) {
+      const int32_t k = big[i];
+      const DevChunk &ch = lv0[k];
+      const int32_t r = hp.fo_chunks[k].dst;
+      const int64_t o = ch.src - win.g0;
+      if (o < 0 || o + ch.n > win.n || o > 0xffff || ch.n < 1 || ch.n > kChunk || hp.fo_chunks[k].src != ch.src)
+        return SF_ERR_ARG;
+      const int32_t first = (k == 0 || hp.fo_chunks[k - 1].dst != r) ? 1 : 0;
+      const int32_t last = (k + 1 == nfo || hp.fo_chunks[k + 1].dst != r) ? 1 : 0;
+      sp.wchunk.push_back({(int32_t)(o | ((int64_t)(ch.n - 1) << 16) | (first << 24) | (last << 25)), ch.dst, r, k});
+    }
+  }
   // scratch slot of every processed leaf: window base + rank in processing order
   std::vector<int32_t> pos(L);
   for (int64_t g = 0; g < L; g++) pos[perm[g]] = (int32_t)g;
@@ -548,8 +571,8 @@ int upload(sf_s *sf) {
     HostPlan::Stage &sp = hp.sp[c];
     DevPlan::Stage &ds = dp.sp[c];
     add(sp.win.data(), sp.win.size() * sizeof(DevSWin), (void **)&ds.win);
-    add(sp.small.data(), sp.small.size() * 4, (void **)&ds.small);
-    add(sp.big.data(), sp.big.size() * 4, (void **)&ds.big);
+    add(sp.sroot.data(), sp.sroot.size() * sizeof(DevSRoot), (void **)&ds.sroot);
+    add(sp.wchunk.data(), sp.wchunk.size() * sizeof(DevWChunk), (void **)&ds.wchunk);
     add(sp.lpos.data(), sp.lpos.size() * 2, (void **)&ds.lpos);
     add(sp.pa_dst.data(), sp.pa_dst.size() * 4, (void **)&ds.pa_dst);
     add(sp.pa_loc.data(), sp.pa_loc.size() * 2, (void **)&ds.pa_loc);

@@ -173,3 +173,22 @@ def test_empty_graph_analysis():
     sf = create(0, []).setup(analyze_only=True)
     info = sf.info()
     assert info["nleaves"] == 0 and info["nroots_touched"] == 0 and info["has_dup_roots"] == 0
+
+
+@pytest.mark.parametrize("case", ["zipf", "holes", "halo", "one_root"])
+def test_partitioned_plan_self_checks(case):
+    """Setup with the partitioned path forced on builds its windows, per-window
+    root and chunk descriptors and pass-A tiles on the host, and checks them
+    (offsets inside their window, the slot map a permutation); a failed check
+    is SF_ERR_ARG."""
+    if case == "zipf":
+        g = inputs.spmv_ghost(seed=3, nroots=20000, nleaves=300001)
+    elif case == "holes":
+        g = inputs.single_sf(seed=11, nroots=5000, nleaves=70001, leafspace=90001)
+    elif case == "halo":
+        g = inputs.halo3d(13)
+    else:
+        n = 200003
+        g = inputs.Graph(2, np.full(n, 1, np.int64), None, np.zeros(n, np.int64), n)
+    sf = create(g.nroots, g.iroot, g.ilocal, g.ranks).setup(partition="on", analyze_only=True)
+    assert sf.info()["nleaves"] == g.nleaves
