@@ -122,12 +122,15 @@ struct HostPlan {
   struct Stage {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     int32_t maxbig = 0;               // most level-0 chunks in one window
+    int32_t maxrun = 0;               // most slot runs in one pass-A tile
     std::vector<DevSWin> win;
     std::vector<DevSRoot> sroot;      // whole roots, window-major (by degree class inside a window)
     std::vector<DevWChunk> wchunk;    // chunks of large roots, window-major, in chunk order
     std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start
-    std::vector<int32_t> pa_dst;      // [L] pass-A tile-major, increasing scratch slot in a tile
-    std::vector<uint16_t> pa_loc;     // [L] tile-local processing offset of that leaf
+    std::vector<uint16_t> pa_loc;     // [L] pass-A tile-major, by increasing scratch slot in a tile: the
+                                      //     tile-local processing offset of that leaf | 0x8000 at a run start
+    std::vector<int32_t> pa_run;      // per run of consecutive slots: first slot minus its tile position
+    std::vector<int32_t> pa_run0;     // [ntiles + 1] first run of each tile
     std::vector<int32_t> tile_leaf0;  // [ntiles] first slot if the tile's slots are contiguous, else -1
     std::vector<int32_t> pa_slot;     // [L] slot per processing position (only if some tile is not contiguous)
   } sp[2];
@@ -151,7 +154,7 @@ struct DevPlan {
     DevSWin *win = nullptr;
     DevSRoot *sroot = nullptr;
     DevWChunk *wchunk = nullptr;
-    int32_t *pa_dst = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
+    int32_t *pa_run = nullptr, *pa_run0 = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
     uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
 };

@@ -27,56 +27,125 @@
 namespace sfi {
 
 // ------------------------------------------------------------ pass A / C
-// DIR 0 (pass A): scratch[slot] = leaf[l];  DIR 1 (pass C): leaf[l] = scratch[slot].
-template <typename Word, int DIR>
-__global__ __launch_bounds__(kStageThreads) void k_sp_move(const int32_t *__restrict__ pa_dst,
-                                                           const uint16_t *__restrict__ pa_loc,
+// A tile's positions are in increasing scratch-slot order, in runs of
+// consecutive slots.  Position jj of a tile lies in run r = (run starts at
+// or before jj) - 1 and goes to slot pa_run[r] + jj.  Thread t takes the
+// positions t + k * kStageThreads (k < P): it loads all their offsets
+// first; each wavefront counts the run starts of its 64 positions with a
+// ballot; one wavefront turns the group counts into exclusive prefixes; the
+// moves follow.  The tile's run offsets are staged in LDS after the tile's
+// units (byte offset run_off) when the tile has at most run_cap runs.
+constexpr int kMoveGroups = 0x8000 / 64;  // most groups of 64 positions in a tile
+// dynamic LDS of a pass-A/C block when two / one of them share a CU (a CU
+// has 160 KB; the group counts take the rest)
+constexpr size_t kMoveLdsTwo = 80 * 1024 - kMoveGroups * 4 - 512;
+constexpr size_t kMoveLdsOne = 160 * 1024 - kMoveGroups * 4 - 512;
+
+template <typename Word, int DIR, int P>
+__global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__restrict__ pa_loc,
+                                                           const int32_t *__restrict__ pa_run0,
+                                                           const int32_t *__restrict__ pa_run,
                                                            const int32_t *__restrict__ tile_leaf0,
                                                            const int32_t *__restrict__ pa_slot, int64_t L, int ta,
                                                            Word *__restrict__ leaf, Word *__restrict__ scratch,
-                                                           int W) {
+                                                           int W, int run_off, int run_cap) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t grp[kMoveGroups];
   Word *lds = reinterpret_cast<Word *>(smem);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * ta;
   const int n = (int)min((int64_t)ta, L - p0);
-  const int items = n * W;
+  const uint16_t *loc = pa_loc + p0;
+  const int32_t *run = pa_run + pa_run0[blockIdx.x];
+  const int nrun = pa_run0[blockIdx.x + 1] - pa_run0[blockIdx.x];
   const int32_t leaf0 = tile_leaf0[blockIdx.x];
-  if (leaf0 >= 0) {
-    const int64_t l0 = (int64_t)leaf0 * W;
-    if (DIR == 0) {
-#pragma unroll 8
-      for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = leaf[l0 + q];
-      __syncthreads();
-#pragma unroll 8
-      for (int q = threadIdx.x; q < items; q += kStageThreads) {
-        const int jj = q / W;
-        const int c = q - jj * W;
-        scratch[(int64_t)pa_dst[p0 + jj] * W + c] = lds[(int)pa_loc[p0 + jj] * W + c];
-      }
-    } else {
-#pragma unroll 8
-      for (int q = threadIdx.x; q < items; q += kStageThreads) {
-        const int jj = q / W;
-        const int c = q - jj * W;
-        lds[(int)pa_loc[p0 + jj] * W + c] = scratch[(int64_t)pa_dst[p0 + jj] * W + c];
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int q = threadIdx.x; q < items; q += kStageThreads) leaf[l0 + q] = lds[q];
-    }
-    return;
+  const int64_t l0 = (int64_t)leaf0 * W;
+  const int items = n * W;
+  int lv[P];
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const int jj = k * kStageThreads + threadIdx.x;
+    lv[k] = jj < n ? (int)loc[jj] : 0;
   }
-  // slots not contiguous: the leaf side is gathered / scattered
-#pragma unroll 4
-  for (int q = threadIdx.x; q < items; q += kStageThreads) {
-    const int jj = q / W;
-    const int c = q - jj * W;
-    const int64_t s = (int64_t)pa_dst[p0 + jj] * W + c;
-    const int64_t l = (int64_t)pa_slot[p0 + pa_loc[p0 + jj]] * W + c;
-    if (DIR == 0)
-      scratch[s] = leaf[l];
-    else
-      leaf[l] = scratch[s];
+  int32_t *rl = reinterpret_cast<int32_t *>(smem + run_off);
+  const bool use_rl = nrun <= run_cap;
+  if (use_rl)
+    for (int i = threadIdx.x; i < nrun; i += kStageThreads) rl[i] = run[i];
+  if (DIR == 0 && leaf0 >= 0) {
+#pragma unroll 8
+    for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = leaf[l0 + q];
+  }
+  // run starts per group of 64 positions (group of position jj: jj >> 6)
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const uint64_t b = __ballot(lv[k] & 0x8000);
+    if (lane == 0) grp[k * (kStageThreads / 64) + wv] = __popcll(b);
+  }
+  __syncthreads();
+  const int ngrp = P * (kStageThreads / 64);
+  if (threadIdx.x < 64) {
+    constexpr int E = kMoveGroups / 64;
+    int v[E];
+    int sum = 0;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int g = lane * E + e;
+      v[e] = g < ngrp ? grp[g] : 0;
+      sum += v[e];
+    }
+    int inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) {
+      const int o = __shfl_up(inc, d);
+      if (lane >= d) inc += o;
+    }
+    int acc = inc - sum;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int g = lane * E + e;
+      if (g < ngrp) grp[g] = acc;
+      acc += v[e];
+    }
+  }
+  __syncthreads();
+  // slots: the run index is kept inside the tile's runs and the slot inside
+  // [0, L), so that a plan that broke its invariants could not make the move
+  // leave its buffers
+  int32_t sl[P];
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const int jj = k * kStageThreads + threadIdx.x;
+    const uint64_t b = __ballot(lv[k] & 0x8000);
+    const int r = min(max(grp[jj >> 6] + __popcll(b & ((2ull << lane) - 1)) - 1, 0), nrun - 1);
+    sl[k] = jj < n ? (use_rl ? rl[r] : run[r]) + jj : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const int64_t slot = sl[k];
+    if (slot < 0 || slot >= L) continue;
+    const int64_t s = slot * W;
+    const int src = (lv[k] & 0x7fff);
+    if (leaf0 >= 0) {
+      for (int c = 0; c < W; c++) {
+        if (DIR == 0)
+          scratch[s + c] = lds[src * W + c];
+        else
+          lds[src * W + c] = scratch[s + c];
+      }
+    } else {  // slots not contiguous: the leaf side is gathered / scattered
+      const int64_t l = (int64_t)pa_slot[p0 + src] * W;
+      for (int c = 0; c < W; c++) {
+        if (DIR == 0)
+          scratch[s + c] = leaf[l + c];
+        else
+          leaf[l + c] = scratch[s + c];
+      }
+    }
+  }
+  if (DIR == 1 && leaf0 >= 0) {
+    __syncthreads();
+#pragma unroll 8
+    for (int q = threadIdx.x; q < items; q += kStageThreads) leaf[l0 + q] = lds[q];
   }
 }
 
@@ -534,17 +603,32 @@ static int allow_lds(const void *fn, size_t bytes) {
 int stage_class(int64_t unit_bytes) { return unit_bytes <= 8 ? 0 : (unit_bytes <= 16 ? 1 : -1); }
 
 // Move whole units between the leaf buffer and scratch (pass A / pass C).
-template <typename Word, int DIR>
-static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st) {
+template <typename Word, int DIR, int P>
+static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st) {
   const HostPlan::Stage &hs = sf->hp.sp[cls];
   const DevPlan::Stage &ds = sf->dp.sp[cls];
   const unsigned g = (unsigned)hs.tile_leaf0.size();
-  const size_t lds = (size_t)hs.ta * W * sizeof(Word);
-  int rc = allow_lds((const void *)&k_sp_move<Word, DIR>, lds);
+  const size_t tile = ((size_t)hs.ta * W * sizeof(Word) + 15) / 16 * 16;
+  const size_t runs = (size_t)hs.maxrun * sizeof(int32_t);
+  // stage the run offsets in LDS when they fit beside the tile (LDS of a CU
+  // less the static group counts), keeping two tiles per CU where a tile
+  // alone would allow it
+  const size_t room = (tile <= kMoveLdsTwo ? kMoveLdsTwo : kMoveLdsOne) - tile;
+  const int run_cap = runs <= room ? hs.maxrun : 0;
+  const size_t lds = tile + (run_cap ? runs : 0);
+  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_sp_move<Word, DIR>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_dst, ds.pa_loc,
-                     ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf, (Word *)scratch, W);
+  hipLaunchKernelGGL((k_sp_move<Word, DIR, P>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc, ds.pa_run0,
+                     ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
+                     (Word *)scratch, W, (int)tile, run_cap);
   return SF_OK;
+}
+template <typename Word, int DIR>
+static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st) {
+  const int ta = sf->hp.sp[cls].ta;  // positions per thread: ta / kStageThreads, at most 32
+  if (ta <= 8 * kStageThreads) return sp_move_p<Word, DIR, 8>(sf, cls, leaf, scratch, W, st);
+  if (ta <= 16 * kStageThreads) return sp_move_p<Word, DIR, 16>(sf, cls, leaf, scratch, W, st);
+  return sp_move_p<Word, DIR, 32>(sf, cls, leaf, scratch, W, st);
 }
 
 static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_t ub, hipStream_t st) {

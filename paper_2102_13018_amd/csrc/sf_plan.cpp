@@ -110,7 +110,7 @@ static DevPattern to_dev(const sf_pattern &p) {
 // Scratch is window-major and, inside a window, in processing order, so:
 //  * pass A, which moves the leaves of `ta` consecutive processing positions
 //    (one pass-A tile) into scratch, writes one contiguous run per window,
-//    in increasing slot order (pa_dst / pa_loc);
+//    in increasing slot order (pa_loc with run starts, pa_run);
 //  * pass B loads one window's contiguous scratch range into LDS, moving
 //    scratch slot s to LDS offset lpos[s] (its sorted position minus the
 //    window's first sorted position).
@@ -219,9 +219,11 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   }
   // pass-A tiles: increasing scratch slot inside each tile
   const int64_t ntiles = (L + ta - 1) / ta;
-  sp.pa_dst.resize(L);
+  if (ta > 0x8000) return SF_ERR_ARG;  // tile offsets take 15 bits
   sp.pa_loc.resize(L);
+  sp.pa_run0.assign(ntiles + 1, 0);
   sp.tile_leaf0.assign(ntiles, -1);
+  std::vector<int32_t> tdst(ta);
   bool gather = false;
   // inside a window, slots increase with processing position, so ordering a
   // tile by slot is a stable counting sort of its leaves by window
@@ -242,11 +244,18 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     for (int32_t w = wlo; w <= whi; w++) cnt[w + 1] += cnt[w];
     for (int64_t q = 0; q < n; q++) {
       const int32_t at = cnt[wofp[p0 + q]]++;
-      sp.pa_dst[p0 + at] = dst[p0 + q];
+      tdst[at] = dst[p0 + q];
       sp.pa_loc[p0 + at] = (uint16_t)q;
     }
-    for (int64_t q = 1; q < n; q++)
-      if (sp.pa_dst[p0 + q] <= sp.pa_dst[p0 + q - 1]) return SF_ERR_ARG;
+    for (int64_t at = 0; at < n; at++) {
+      if (at > 0 && tdst[at] <= tdst[at - 1]) return SF_ERR_ARG;
+      if (at == 0 || tdst[at] != tdst[at - 1] + 1) {  // a new run of consecutive slots
+        sp.pa_loc[p0 + at] |= 0x8000;
+        sp.pa_run.push_back(tdst[at] - (int32_t)at);
+      }
+    }
+    sp.pa_run0[k + 1] = (int32_t)sp.pa_run.size();
+    sp.maxrun = std::max(sp.maxrun, sp.pa_run0[k + 1] - sp.pa_run0[k]);
     if (contiguous) sp.tile_leaf0[k] = proc_slot[p0];
     else gather = true;
   }
@@ -574,7 +583,8 @@ int upload(sf_s *sf) {
     add(sp.sroot.data(), sp.sroot.size() * sizeof(DevSRoot), (void **)&ds.sroot);
     add(sp.wchunk.data(), sp.wchunk.size() * sizeof(DevWChunk), (void **)&ds.wchunk);
     add(sp.lpos.data(), sp.lpos.size() * 2, (void **)&ds.lpos);
-    add(sp.pa_dst.data(), sp.pa_dst.size() * 4, (void **)&ds.pa_dst);
+    add(sp.pa_run.data(), sp.pa_run.size() * 4, (void **)&ds.pa_run);
+    add(sp.pa_run0.data(), sp.pa_run0.size() * 4, (void **)&ds.pa_run0);
     add(sp.pa_loc.data(), sp.pa_loc.size() * 2, (void **)&ds.pa_loc);
     add(sp.tile_leaf0.data(), sp.tile_leaf0.size() * 4, (void **)&ds.tile_leaf0);
     add(sp.pa_slot.data(), sp.pa_slot.size() * 4, (void **)&ds.pa_slot);
