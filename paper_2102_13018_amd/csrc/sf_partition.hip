@@ -41,6 +41,18 @@ constexpr int kMoveGroups = 0x8000 / 64;  // most groups of 64 positions in a ti
 constexpr size_t kMoveLdsTwo = 80 * 1024 - kMoveGroups * 4 - 512;
 constexpr size_t kMoveLdsOne = 160 * 1024 - kMoveGroups * 4 - 512;
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
+// b % 8), each XCD with its own L2.  Neighbouring tiles write and read the
+// two halves of the same cache lines of a window (their runs are adjacent),
+// so every XCD takes a contiguous share of the tiles: workgroup b gets tile
+// b / 8 of XCD b % 8's share.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n % X;
+  const int x = b % X, i = b / X;
+  return x * q + min(x, r) + i;
+}
+
 template <typename Word, int DIR, int P>
 __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__restrict__ pa_loc,
                                                            const int32_t *__restrict__ pa_run0,
@@ -53,12 +65,13 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
   __shared__ int32_t grp[kMoveGroups];
   Word *lds = reinterpret_cast<Word *>(smem);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t p0 = (int64_t)blockIdx.x * ta;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t p0 = (int64_t)tile * ta;
   const int n = (int)min((int64_t)ta, L - p0);
   const uint16_t *loc = pa_loc + p0;
-  const int32_t *run = pa_run + pa_run0[blockIdx.x];
-  const int nrun = pa_run0[blockIdx.x + 1] - pa_run0[blockIdx.x];
-  const int32_t leaf0 = tile_leaf0[blockIdx.x];
+  const int32_t *run = pa_run + pa_run0[tile];
+  const int nrun = pa_run0[tile + 1] - pa_run0[tile];
+  const int32_t leaf0 = tile_leaf0[tile];
   const int64_t l0 = (int64_t)leaf0 * W;
   const int items = n * W;
   int lv[P];
