@@ -82,7 +82,11 @@ typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4
  *                  than the atomic one); FetchAndOp on FP units and batch
  *                  items with roots of more than 256 leaves use atomics;
  *  ATOMIC        : native atomics, with block-local aggregation of the
- *                  roots of highest degree; FP SUM order is unspecified;
+ *                  roots of highest degree; on a partitioned SF (below) a
+ *                  root whose leaves all fall in one window is updated
+ *                  plainly and a root spanning windows takes one native
+ *                  atomic per window (FetchAndOp: a returning atomic add);
+ *                  FP SUM order is unspecified;
  *  DETERMINISTIC : root-sorted segmented reduction; FP SUM is the
  *                  canonical pairwise sum of the root's leaves in ascending
  *                  leaf index, added to the root (root on the left);
@@ -95,8 +99,10 @@ typedef struct {
   int32_t reduce_mode;  /* sf_reduce_mode, default AUTO */
   int32_t use_patterns; /* 1 (default): detect contiguous / 3-D sub-block index patterns */
   int32_t analyze_only; /* 1: host analysis only, no device memory (for inspection) */
-  int32_t partition;    /* deterministic path through bucket-major scratch: 0 auto (SFs of
-                           2^20 leaves or more), 1 always, 2 never; results are identical */
+  int32_t partition;    /* Reduce / FetchAndOp through window-major scratch (units of at most
+                           16 bytes, SFs with repeated roots): 0 auto (SFs of 2^20 leaves or
+                           more), 1 always, 2 never.  Deterministic results are identical
+                           either way; atomic results meet the same bar either way. */
 } sf_setup_opts;
 
 /* Index pattern of one side of one segment (Section 5.2): index(t) for the
