@@ -140,8 +140,8 @@ def build_spmv_ops(torch, S, inputs, g):
         Op("reduce_maxloc_det", red("deterministic", lpair, rpair, "maxloc", upair), r8(16),
            "k_sp_move + k_sp_reduce + k_det_chunk"),
         Op("fetch_and_op_i64_det", fop("deterministic"), f8(8),
-           "k_sp_move + k_sp_fop_b1 + k_fop_root_scan + k_sp_fop_b3 + k_sp_move"),
-        Op("fetch_and_op_i64_atomic", fop("atomic"), f8(8), "k_sp_move + k_sp_fop_atomic + k_sp_move"),
+           "k_sp_move + k_sp_fop<det> + k_sp_span_scan + k_sp_move<add bases>"),
+        Op("fetch_and_op_i64_atomic", fop("atomic"), f8(8), "k_sp_move + k_sp_fop<atomic> + k_sp_move"),
     ]
     direct = [
         Op("reduce_sum_f64_atomic_direct", red("atomic", xl64, xr64, "sum", u64, sfd), r8(8), "k_reduce_atomic"),

@@ -127,10 +127,17 @@ struct HostPlan {
     std::vector<DevSRoot> sroot;      // whole roots, window-major (by degree class inside a window)
     std::vector<DevWChunk> wchunk;    // chunks of large roots, window-major, in chunk order
     std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start
+                                      //     (< 2^14) | 0x8000 in a run of a root that spans
+                                      //     windows | 0x4000 if that run continues into the next
     std::vector<uint16_t> pa_loc;     // [L] pass-A tile-major, by increasing scratch slot in a tile: the
                                       //     tile-local processing offset of that leaf | 0x8000 at a run start
     std::vector<int32_t> pa_run;      // per run of consecutive slots: first slot minus its tile position
     std::vector<int32_t> pa_run0;     // [ntiles + 1] first run of each tile
+    std::vector<int32_t> pa_runw;     // per run: its window
+    // roots whose chunks span windows: their runs (2 * window + which) in window order
+    std::vector<int32_t> span_first;  // [nspan + 1]
+    std::vector<int32_t> span_slot;
+    std::vector<int32_t> span_root;   // [nspan]
     std::vector<int32_t> tile_leaf0;  // [ntiles] first slot if the tile's slots are contiguous, else -1
     std::vector<int32_t> pa_slot;     // [L] slot per processing position (only if some tile is not contiguous)
   } sp[2];
@@ -155,6 +162,7 @@ struct DevPlan {
     DevSRoot *sroot = nullptr;
     DevWChunk *wchunk = nullptr;
     int32_t *pa_run = nullptr, *pa_run0 = nullptr, *tile_leaf0 = nullptr, *pa_slot = nullptr;
+    int32_t *pa_runw = nullptr, *span_first = nullptr, *span_slot = nullptr, *span_root = nullptr;
     uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
 };

@@ -53,14 +53,43 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + i;
 }
 
-template <typename Word, int DIR, int P>
+// Pass C of the deterministic FetchAndOp adds, to every element of a slot
+// in a run of a root that spans windows (0x8000 in lpos), that run's base:
+// rbase[(2 * window + which) * W + element], which = bit 14 of lpos, window
+// = the window of the slot's pass-C run (staged in LDS beside the run
+// offsets).  FIX is the element size (4 or 8 bytes, integer units; one Word
+// per element) or 0 for a plain move.
+template <int FIX, typename Word>
+__device__ __forceinline__ Word add_word(Word v, Word b) {
+  if constexpr (FIX == 4) {
+    return (Word)((uint32_t)v + (uint32_t)b);
+  } else {
+    const uint64_t r = (((uint64_t)v.y << 32) | v.x) + (((uint64_t)b.y << 32) | b.x);
+    Word o;
+    o.x = (uint32_t)r;
+    o.y = (uint32_t)(r >> 32);
+    return o;
+  }
+}
+template <int FIX, typename Word>
+__device__ __forceinline__ Word add_base(Word v, const void *rbase, int64_t e) {
+  return add_word<FIX>(v, reinterpret_cast<const Word *>(rbase)[e]);
+}
+
+struct MoveFix {
+  const uint16_t *lpos;
+  const int32_t *pa_runw;
+  const void *rbase;
+};
+
+template <typename Word, int DIR, int P, int FIX>
 __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__restrict__ pa_loc,
                                                            const int32_t *__restrict__ pa_run0,
                                                            const int32_t *__restrict__ pa_run,
                                                            const int32_t *__restrict__ tile_leaf0,
                                                            const int32_t *__restrict__ pa_slot, int64_t L, int ta,
                                                            Word *__restrict__ leaf, Word *__restrict__ scratch,
-                                                           int W, int run_off, int run_cap) {
+                                                           int W, int run_off, int run_cap, MoveFix fx) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t grp[kMoveGroups];
   Word *lds = reinterpret_cast<Word *>(smem);
@@ -81,9 +110,13 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
     lv[k] = jj < n ? (int)loc[jj] : 0;
   }
   int32_t *rl = reinterpret_cast<int32_t *>(smem + run_off);
+  int32_t *rw = rl + run_cap;  // FIX: the runs' windows
   const bool use_rl = nrun <= run_cap;
-  if (use_rl)
+  if (use_rl) {
     for (int i = threadIdx.x; i < nrun; i += kStageThreads) rl[i] = run[i];
+    if constexpr (FIX != 0)
+      for (int i = threadIdx.x; i < nrun; i += kStageThreads) rw[i] = fx.pa_runw[pa_run0[tile] + i];
+  }
   if (DIR == 0 && leaf0 >= 0) {
 #pragma unroll 8
     for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = leaf[l0 + q];
@@ -125,12 +158,36 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
   // [0, L), so that a plan that broke its invariants could not make the move
   // leave its buffers
   int32_t sl[P];
+  int32_t rr[FIX ? P : 1];
 #pragma unroll
   for (int k = 0; k < P; k++) {
     const int jj = k * kStageThreads + threadIdx.x;
     const uint64_t b = __ballot(lv[k] & 0x8000);
     const int r = min(max(grp[jj >> 6] + __popcll(b & ((2ull << lane) - 1)) - 1, 0), nrun - 1);
     sl[k] = jj < n ? (use_rl ? rl[r] : run[r]) + jj : -1;
+    if constexpr (FIX != 0) rr[k] = r;
+  }
+  // FIX: the first rbase element of each slot's run (-1: none), and for
+  // one-word units the base itself, loaded together ahead of the moves
+  int64_t fes[FIX ? P : 1];
+  Word fb[FIX ? P : 1];
+  if constexpr (FIX != 0) {
+    int lp[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) lp[k] = (sl[k] >= 0 && sl[k] < L) ? (int)fx.lpos[sl[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      fes[k] = -1;
+      if (lp[k] & 0x8000) {
+        const int w = use_rl ? rw[rr[k]] : fx.pa_runw[pa_run0[tile] + rr[k]];
+        fes[k] = (int64_t)(2 * w + ((lp[k] >> 14) & 1)) * W;
+      }
+    }
+    if (W == 1) {
+#pragma unroll
+      for (int k = 0; k < P; k++)
+        if (fes[k] >= 0) fb[k] = reinterpret_cast<const Word *>(fx.rbase)[fes[k]];
+    }
   }
 #pragma unroll
   for (int k = 0; k < P; k++) {
@@ -138,20 +195,38 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
     if (slot < 0 || slot >= L) continue;
     const int64_t s = slot * W;
     const int src = (lv[k] & 0x7fff);
+    int64_t fe = -1;  // FIX: first rbase element of the slot's run, if it has one
+    if constexpr (FIX != 0) fe = fes[k];
+    if constexpr (FIX != 0) {
+      if (W == 1 && leaf0 >= 0) {  // one-word units: the base is already loaded
+        Word v = scratch[s];
+        if (fe >= 0) v = add_word<FIX>(v, fb[k]);
+        lds[src] = v;
+        continue;
+      }
+    }
     if (leaf0 >= 0) {
       for (int c = 0; c < W; c++) {
-        if (DIR == 0)
+        if (DIR == 0) {
           scratch[s + c] = lds[src * W + c];
-        else
-          lds[src * W + c] = scratch[s + c];
+        } else {
+          Word v = scratch[s + c];
+          if constexpr (FIX != 0)
+            if (fe >= 0) v = add_base<FIX>(v, fx.rbase, fe + c);
+          lds[src * W + c] = v;
+        }
       }
     } else {  // slots not contiguous: the leaf side is gathered / scattered
       const int64_t l = (int64_t)pa_slot[p0 + src] * W;
       for (int c = 0; c < W; c++) {
-        if (DIR == 0)
+        if (DIR == 0) {
           scratch[s + c] = leaf[l + c];
-        else
-          leaf[l + c] = scratch[s + c];
+        } else {
+          Word v = scratch[s + c];
+          if constexpr (FIX != 0)
+            if (fe >= 0) v = add_base<FIX>(v, fx.rbase, fe + c);
+          leaf[l + c] = v;
+        }
       }
     }
   }
@@ -163,7 +238,8 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
 }
 
 // Load one window from scratch into LDS in root-sorted order (LDS offset =
-// sorted position - window start), and store it back.  Global accesses are
+// sorted position - window start, the low 14 bits of lpos), and store it
+// back.  Global accesses are
 // coalesced; the permutation happens in LDS.
 template <typename T>
 __device__ __forceinline__ void win_load(T *lds, const T *__restrict__ scr, const uint16_t *__restrict__ lpos,
@@ -171,13 +247,13 @@ __device__ __forceinline__ void win_load(T *lds, const T *__restrict__ scr, cons
   const T *src = scr + (int64_t)w.base * bs;
   if (bs == 1) {
 #pragma unroll 8
-    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q]] = src[q];
+    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q] & 0x3fff] = src[q];
   } else {
     const int items = w.n * bs;
 #pragma unroll 4
     for (int q = threadIdx.x; q < items; q += kStageThreads) {
       const int k = q / bs;
-      lds[(int)lpos[w.base + k] * bs + (q - k * bs)] = src[q];
+      lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)] = src[q];
     }
   }
 }
@@ -189,7 +265,7 @@ __device__ __forceinline__ void win_store(const T *lds, T *__restrict__ scr, con
 #pragma unroll 4
   for (int q = threadIdx.x; q < items; q += kStageThreads) {
     const int k = q / bs;
-    dst[q] = lds[(int)lpos[w.base + k] * bs + (q - k * bs)];
+    dst[q] = lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)];
   }
 }
 
@@ -408,47 +484,6 @@ __device__ __forceinline__ void small_scan(T *lds, const DevSRoot *__restrict__ 
   }
 }
 
-// B1: whole roots as above; chunks of large roots write their sums.
-template <typename T>
-__global__ __launch_bounds__(kStageThreads) void k_sp_fop_b1(const DevSWin *__restrict__ wins,
-                                                             const DevSRoot *__restrict__ sroot,
-                                                             const DevWChunk *__restrict__ wchunk,
-                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
-                                                             T *__restrict__ sums, T *__restrict__ root, int bs,
-                                                             int cd_off) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *lds = reinterpret_cast<T *>(smem);
-  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
-  const DevSWin win = wins[blockIdx.x];
-  const int nsmall = (win.small1 - win.small0) * bs;
-  const int nb = win.big1 - win.big0;
-  DevSRoot sd[kSmallU];
-  T rv[kSmallU];
-  small_fetch(sroot, (const T *)root, win, threadIdx.x, nsmall, bs, sd, rv);
-  for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
-  win_load(lds, scr, lpos, win, bs);
-  __syncthreads();
-  if (nsmall > 0) small_scan(lds, sroot, root, win, nsmall, bs, sd, rv);
-  constexpr int LPT = kChunkLPT;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j = wv; j < nb; j += kStageThreads / 64) {
-    const DevWChunk ch = cd[j];
-    const int n = wc_n(ch.onf);
-    const int o = wc_off(ch.onf) + lane * LPT;
-    for (int c = 0; c < bs; c++) {
-      T a = T(0);
-#pragma unroll
-      for (int s = 0; s < LPT; s++)
-        if (lane * LPT + s < n) a = Op<OP_SUM, T>::apply(a, lds[(o + s) * bs + c]);
-#pragma unroll
-      for (int d = 32; d >= 1; d /= 2) a = Op<OP_SUM, T>::apply(a, shfl_down(a, d));
-      if (lane == 0) sums[(int64_t)ch.k * bs + c] = a;
-    }
-  }
-  __syncthreads();
-  if (nsmall > 0) win_store(lds, scr, lpos, win, bs);
-}
-
 // Exclusive prefix inside chunk j of the window plus the chunk's base
 // (from LDS), written over the chunk's values.
 template <typename T>
@@ -485,47 +520,24 @@ __device__ __forceinline__ void chunk_apply(T *lds, const DevWChunk *cd, const T
   }
 }
 
-// B3: chunks of large roots take their base from the root scan.
-template <typename T>
-__global__ __launch_bounds__(kStageThreads) void k_sp_fop_b3(const DevSWin *__restrict__ wins,
-                                                             const DevWChunk *__restrict__ wchunk,
-                                                             const uint16_t *__restrict__ lpos, T *__restrict__ scr,
-                                                             const T *__restrict__ sums, int bs, int cd_off,
-                                                             int cv_off) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *lds = reinterpret_cast<T *>(smem);
-  DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
-  T *cv = reinterpret_cast<T *>(smem + cv_off);
-  const DevSWin win = wins[blockIdx.x];
-  const int nb = win.big1 - win.big0;
-  if (nb == 0) return;
-  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
-    const int j = q / bs, c = q - j * bs;
-    const DevWChunk d = wchunk[win.big0 + j];
-    if (c == 0) cd[j] = d;
-    cv[q] = sums[(int64_t)d.k * bs + c];
-  }
-  win_load(lds, scr, lpos, win, bs);
-  __syncthreads();
-  chunk_apply(lds, cd, cv, nb, bs);
-  __syncthreads();
-  win_store(lds, scr, lpos, win, bs);
-}
-
-// ------------------------------------------------- pass B FetchAndOp, atomic
-// One pass: whole roots as in B1.  The chunks of a large root that lie in
-// this window form a run: their totals give every chunk its offset inside
-// the run, and the run takes its base from the root -- plainly when the run
-// is the whole root, else with one native returning atomic add, so the
-// windows of a spanning root are applied in arrival order while the leaves
-// inside a window keep leaf order.
-template <typename T>
-__global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *__restrict__ wins,
-                                                                 const DevSRoot *__restrict__ sroot,
-                                                                 const DevWChunk *__restrict__ wchunk,
-                                                                 const uint16_t *__restrict__ lpos,
-                                                                 T *__restrict__ scr, T *__restrict__ root, int bs,
-                                                                 int cd_off, int cv_off) {
+// One pass over a window.  Whole roots scan sequentially in leaf order.  The
+// chunks of a large root that lie in this window form a run: their totals
+// give every chunk its offset inside the run, and the leaves inside a chunk
+// take the chunk's offset plus their exclusive prefix.  A run that is the
+// whole root takes its base from the root plainly.  A run of a root that
+// spans windows takes, in atomic mode (ATOM), its base from one native
+// returning atomic add, so the windows of such a root are applied in
+// arrival order; in deterministic mode it takes base 0 and leaves its total
+// in rtot[2 * window + which] (which 0: the run continues a root from the
+// previous window, 1: it continues into the next), for the scan over the
+// root's windows and the base that pass C adds.
+template <typename T, bool ATOM>
+__global__ __launch_bounds__(kStageThreads) void k_sp_fop(const DevSWin *__restrict__ wins,
+                                                          const DevSRoot *__restrict__ sroot,
+                                                          const DevWChunk *__restrict__ wchunk,
+                                                          const uint16_t *__restrict__ lpos, T *__restrict__ scr,
+                                                          T *__restrict__ root, T *__restrict__ rtot, int bs,
+                                                          int cd_off, int cv_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *lds = reinterpret_cast<T *>(smem);
   DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
@@ -559,7 +571,7 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *
       }
     }
     __syncthreads();
-    // 2: per run, chunk offsets inside the run and the run's base from the root
+    // 2: per run, chunk offsets inside the run and the run's base
     for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
       const int j = q / bs, c = q - j * bs;
       const int32_t r = cd[j].root;
@@ -576,8 +588,12 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *
       if (wc_first(cd[j].onf) && wc_last(cd[j1 - 1].onf)) {
         base = *rp;
         *rp = Op<OP_SUM, T>::apply(base, run);
-      } else {
+      } else if constexpr (ATOM) {
         base = fetch_add_g(rp, run);
+      } else {
+        const int which = wc_off(cd[j].onf) == 0 ? 0 : 1;
+        rtot[(int64_t)(2 * blockIdx.x + which) * bs + c] = run;
+        base = T(0);
       }
       for (int jj = j; jj < j1; jj++) cv[jj * bs + c] = Op<OP_SUM, T>::apply(base, cv[jj * bs + c]);
     }
@@ -587,6 +603,40 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop_atomic(const DevSWin *
   }
   __syncthreads();
   win_store(lds, scr, lpos, win, bs);
+}
+
+// Deterministic FetchAndOp across windows: one wavefront per root that
+// spans windows turns its runs' totals (in window order, i.e. leaf order)
+// into their bases, starting from the root's value, and leaves the root's
+// final value.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sp_span_scan(const int32_t *__restrict__ span_first,
+                                                         const int32_t *__restrict__ span_slot,
+                                                         const int32_t *__restrict__ span_root, int nspan,
+                                                         const T *__restrict__ rtot, T *__restrict__ rbase,
+                                                         T *__restrict__ root, int bs) {
+  const int lane = threadIdx.x & 63;
+  const int i = (int)((blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6);
+  if (i >= nspan) return;
+  const int a = span_first[i], b = span_first[i + 1];
+  T *rp = root + (int64_t)span_root[i] * bs;
+  for (int c = 0; c < bs; c++) {
+    T carry = rp[c];
+    for (int k0 = a; k0 < b; k0 += 64) {
+      const int k = k0 + lane;
+      const int64_t e = k < b ? (int64_t)span_slot[k] * bs + c : 0;
+      const T v = k < b ? rtot[e] : T(0);
+      T inc = v;
+#pragma unroll
+      for (int d = 1; d < 64; d *= 2) {
+        const T o = shfl_up(inc, d);
+        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
+      }
+      if (k < b) rbase[e] = Op<OP_SUM, T>::apply(carry, wrap_sub(inc, v));
+      carry = Op<OP_SUM, T>::apply(carry, shfl_idx(inc, 63));
+    }
+    if (lane == 0) rp[c] = carry;
+  }
 }
 
 // ================================================================ launchers
@@ -616,32 +666,32 @@ static int allow_lds(const void *fn, size_t bytes) {
 int stage_class(int64_t unit_bytes) { return unit_bytes <= 8 ? 0 : (unit_bytes <= 16 ? 1 : -1); }
 
 // Move whole units between the leaf buffer and scratch (pass A / pass C).
-template <typename Word, int DIR, int P>
-static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st) {
+template <typename Word, int DIR, int P, int FIX>
+static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx) {
   const HostPlan::Stage &hs = sf->hp.sp[cls];
   const DevPlan::Stage &ds = sf->dp.sp[cls];
   const unsigned g = (unsigned)hs.tile_leaf0.size();
   const size_t tile = ((size_t)hs.ta * W * sizeof(Word) + 15) / 16 * 16;
-  const size_t runs = (size_t)hs.maxrun * sizeof(int32_t);
+  const size_t runs = (size_t)hs.maxrun * sizeof(int32_t) * (FIX ? 2 : 1);  // offsets (and windows)
   // stage the run offsets in LDS when they fit beside the tile (LDS of a CU
   // less the static group counts), keeping two tiles per CU where a tile
   // alone would allow it
   const size_t room = (tile <= kMoveLdsTwo ? kMoveLdsTwo : kMoveLdsOne) - tile;
   const int run_cap = runs <= room ? hs.maxrun : 0;
   const size_t lds = tile + (run_cap ? runs : 0);
-  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P>, lds);
+  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_sp_move<Word, DIR, P>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc, ds.pa_run0,
+  hipLaunchKernelGGL((k_sp_move<Word, DIR, P, FIX>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc, ds.pa_run0,
                      ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
-                     (Word *)scratch, W, (int)tile, run_cap);
+                     (Word *)scratch, W, (int)tile, run_cap, fx);
   return SF_OK;
 }
-template <typename Word, int DIR>
-static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st) {
+template <typename Word, int DIR, int FIX = 0>
+static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx = MoveFix{}) {
   const int ta = sf->hp.sp[cls].ta;  // positions per thread: ta / kStageThreads, at most 32
-  if (ta <= 8 * kStageThreads) return sp_move_p<Word, DIR, 8>(sf, cls, leaf, scratch, W, st);
-  if (ta <= 16 * kStageThreads) return sp_move_p<Word, DIR, 16>(sf, cls, leaf, scratch, W, st);
-  return sp_move_p<Word, DIR, 32>(sf, cls, leaf, scratch, W, st);
+  if (ta <= 8 * kStageThreads) return sp_move_p<Word, DIR, 8, FIX>(sf, cls, leaf, scratch, W, st, fx);
+  if (ta <= 16 * kStageThreads) return sp_move_p<Word, DIR, 16, FIX>(sf, cls, leaf, scratch, W, st, fx);
+  return sp_move_p<Word, DIR, 32, FIX>(sf, cls, leaf, scratch, W, st, fx);
 }
 
 static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_t ub, hipStream_t st) {
@@ -735,41 +785,43 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
   const int cls = stage_class((int64_t)ub);
   const HostPlan::Stage &hs = h.sp[cls];
   const DevPlan::Stage &ds = d.sp[cls];
-  const int nch = (int)h.fo_chunks.size();
-  const int nlarge = (int)h.large.size();
+  const unsigned gw = (unsigned)hs.win.size();
+  const bool det = !atomic && std::is_integral<T>::value;  // floating point: atomic only
+  // scratch: window-major leaf units, then run totals and run bases (2 per window)
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
-  int rc = ensure_scratch(sf, main_bytes + (size_t)std::max(nch, 1) * ub);
+  const size_t runs_bytes = ((size_t)2 * gw * ub + 255) / 256 * 256;
+  int rc = ensure_scratch(sf, main_bytes + (det ? 2 * runs_bytes : 0));
   if (rc) return rc;
   T *scr = (T *)sf->scratch;
-  T *sums = (T *)((char *)sf->scratch + main_bytes);
-  const unsigned gw = (unsigned)hs.win.size();
+  T *rtot = (T *)((char *)sf->scratch + main_bytes);
+  T *rbase = (T *)((char *)sf->scratch + main_bytes + runs_bytes);
   const PassBLds pl = passb_lds(hs, ub);
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
-  if (atomic || !std::is_integral<T>::value) {  // floating point: atomic only
-    if ((rc = allow_lds((const void *)&k_sp_fop_atomic<T>, pl.bytes))) return rc;
-    hipLaunchKernelGGL((k_sp_fop_atomic<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
-                       ds.wchunk, ds.lpos, scr, root, bs, pl.cd_off, pl.cv_off);
+  if (!det) {
+    if ((rc = allow_lds((const void *)&k_sp_fop<T, true>, pl.bytes))) return rc;
+    hipLaunchKernelGGL((k_sp_fop<T, true>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot, ds.wchunk,
+                       ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
     rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
     if (rc) return rc;
     return sp_check();
   }
   if constexpr (std::is_integral<T>::value) {
-    if ((rc = allow_lds((const void *)&k_sp_fop_b1<T>, pl.bytes))) return rc;
-    if ((rc = allow_lds((const void *)&k_sp_fop_b3<T>, pl.bytes))) return rc;
-    hipLaunchKernelGGL((k_sp_fop_b1<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot, ds.wchunk,
-                       ds.lpos, scr, sums, root, bs, pl.cd_off);
-    if (nch) {
-      hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock),
-                         0, st, d.fo_root_first, nlarge, d.fo_chunks, sums, root, bs);
-      hipLaunchKernelGGL((k_sp_fop_b3<T>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.wchunk, ds.lpos,
-                         scr, (const T *)sums, bs, pl.cd_off, pl.cv_off);
-    }
-    rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
+    if ((rc = allow_lds((const void *)&k_sp_fop<T, false>, pl.bytes))) return rc;
+    hipLaunchKernelGGL((k_sp_fop<T, false>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
+                       ds.wchunk, ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
+    const int nspan = (int)hs.span_root.size();
+    if (nspan)
+      hipLaunchKernelGGL((k_sp_span_scan<T>), dim3((unsigned)((nspan * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                         st, ds.span_first, ds.span_slot, ds.span_root, nspan, (const T *)rtot, rbase, root, bs);
+    // pass C with the run bases added: one word per element
+    using EW = typename std::conditional<sizeof(T) == 4, uint32_t, uint2>::type;
+    const MoveFix fx{ds.lpos, ds.pa_runw, rbase};
+    rc = sp_move_w<EW, 1, (int)sizeof(T)>(sf, cls, (void *)upd, scr, bs, st, fx);
     if (rc) return rc;
     return sp_check();
   }
-  return SF_ERR_UNSUPPORTED;  // deterministic FetchAndOp is defined for integers only
+  return SF_ERR_UNSUPPORTED;
 }
 
 template int launch_reduce_part<double, OP_SUM>(sf_s *, const double *, double *, int, bool, hipStream_t);

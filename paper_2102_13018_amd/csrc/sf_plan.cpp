@@ -211,12 +211,46 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     dst[p] = cursor[win_g[pos[i]]]++;
   }
   sp.lpos.assign(L, 0);
+  std::vector<int32_t> slot_of_g(L);
   for (int64_t g = 0; g < L; g++) {
     const DevSWin &w = sp.win[win_g[g]];
     const int64_t s = dst[proc_of_leaf[perm[g]]];
-    if (s < w.base || s >= (int64_t)w.base + w.n || g - w.g0 > 65535) return SF_ERR_ARG;
+    if (s < w.base || s >= (int64_t)w.base + w.n || g - w.g0 > 0x3fff) return SF_ERR_ARG;
     sp.lpos[s] = (uint16_t)(g - w.g0);
+    slot_of_g[g] = (int32_t)s;
   }
+  // Runs of a large root's chunks inside a window that are not the whole root
+  // span windows.  Such a run starts at the window's first sorted position
+  // (it continues one from the previous window; "which" 0) or ends at its
+  // last (it continues into the next; which 1).  Their slots carry 0x8000 |
+  // which << 14 in lpos, and every spanning root lists its runs
+  // (2 * window + which) in window order.
+  sp.span_first.assign(1, 0);
+  for (int64_t w = 0; w < W; w++) {
+    const DevSWin &win = sp.win[w];
+    bool have0 = false;
+    for (int32_t i = win.big0; i < win.big1;) {
+      const DevWChunk &c0 = sp.wchunk[i];
+      int32_t j = i + 1;
+      while (j < win.big1 && sp.wchunk[j].root == c0.root) j++;
+      const DevWChunk &c1 = sp.wchunk[j - 1];
+      const bool whole = ((c0.onf >> 24) & 1) && ((c1.onf >> 25) & 1);
+      if (!whole) {
+        const int32_t o0 = c0.onf & 0xffff, o1 = (c1.onf & 0xffff) + ((c1.onf >> 16) & 0xff) + 1;
+        const int32_t which = o0 == 0 ? 0 : 1;
+        if ((which == 0 && have0) || (which == 1 && o1 != win.n)) return SF_ERR_ARG;
+        have0 = have0 || which == 0;
+        for (int32_t o = o0; o < o1; o++) sp.lpos[slot_of_g[win.g0 + o]] |= (uint16_t)(0x8000 | (which << 14));
+        if (sp.span_root.empty() || sp.span_root.back() != c0.root) {
+          if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
+          sp.span_root.push_back(c0.root);
+        }
+        sp.span_slot.push_back((int32_t)(2 * w + which));
+      }
+      i = j;
+    }
+  }
+  if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
   // pass-A tiles: increasing scratch slot inside each tile
   const int64_t ntiles = (L + ta - 1) / ta;
   if (ta > 0x8000) return SF_ERR_ARG;  // tile offsets take 15 bits
@@ -249,9 +283,12 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     }
     for (int64_t at = 0; at < n; at++) {
       if (at > 0 && tdst[at] <= tdst[at - 1]) return SF_ERR_ARG;
-      if (at == 0 || tdst[at] != tdst[at - 1] + 1) {  // a new run of consecutive slots
+      // a new run of consecutive slots, also where the window changes
+      const int32_t w_at = wofp[p0 + sp.pa_loc[p0 + at]];
+      if (at == 0 || tdst[at] != tdst[at - 1] + 1 || w_at != sp.pa_runw.back()) {
         sp.pa_loc[p0 + at] |= 0x8000;
         sp.pa_run.push_back(tdst[at] - (int32_t)at);
+        sp.pa_runw.push_back(w_at);
       }
     }
     sp.pa_run0[k + 1] = (int32_t)sp.pa_run.size();
@@ -584,6 +621,10 @@ int upload(sf_s *sf) {
     add(sp.wchunk.data(), sp.wchunk.size() * sizeof(DevWChunk), (void **)&ds.wchunk);
     add(sp.lpos.data(), sp.lpos.size() * 2, (void **)&ds.lpos);
     add(sp.pa_run.data(), sp.pa_run.size() * 4, (void **)&ds.pa_run);
+    add(sp.pa_runw.data(), sp.pa_runw.size() * 4, (void **)&ds.pa_runw);
+    add(sp.span_first.data(), sp.span_first.size() * 4, (void **)&ds.span_first);
+    add(sp.span_slot.data(), sp.span_slot.size() * 4, (void **)&ds.span_slot);
+    add(sp.span_root.data(), sp.span_root.size() * 4, (void **)&ds.span_root);
     add(sp.pa_run0.data(), sp.pa_run0.size() * 4, (void **)&ds.pa_run0);
     add(sp.pa_loc.data(), sp.pa_loc.size() * 2, (void **)&ds.pa_loc);
     add(sp.tile_leaf0.data(), sp.tile_leaf0.size() * 4, (void **)&ds.tile_leaf0);
