@@ -62,8 +62,9 @@ typedef enum {
 } sf_copymode;
 
 /* Element type of a unit.  SF_F64_I32 is the MAXLOC pair
- * struct { double v; int32_t i; int32_t pad; } with a 16-byte extent; pad is
- * never read or written. */
+ * struct { double v; int32_t i; int32_t pad; } with a 16-byte extent; pad
+ * never affects a result and is never written in the caller's roots or leaves
+ * (large SFs copy whole 16-byte leaf units, pad included, into scratch). */
 typedef enum { SF_F64 = 0, SF_F32 = 1, SF_I32 = 2, SF_I64 = 3, SF_F64_I32 = 4 } sf_dtype;
 
 /* A unit is bs contiguous elements of one dtype: the "unit" MPI datatype of

@@ -28,6 +28,14 @@ __device__ __forceinline__ uint32_t fkey(float x) {
   return b < 0 ? ~(uint32_t)b : ((uint32_t)b | 0x80000000u);
 }
 
+// Inverse of fkey.
+__device__ __forceinline__ double fkey_inv(uint64_t k) {
+  return __longlong_as_double((long long)(k & 0x8000000000000000ull ? k & 0x7fffffffffffffffull : ~k));
+}
+__device__ __forceinline__ float fkey_inv(uint32_t k) {
+  return __int_as_float((int)(k & 0x80000000u ? k & 0x7fffffffu : ~k));
+}
+
 enum OpCode { OP_REPLACE = SF_REPLACE, OP_SUM = SF_SUM, OP_MAX = SF_MAX, OP_MIN = SF_MIN, OP_MAXLOC = SF_MAXLOC };
 
 // a (left operand) op b
@@ -68,6 +76,21 @@ struct Op<OP, int64_t> {
     if (OP == OP_MAX) return a < b ? b : a;
     if (OP == OP_MIN) return b < a ? b : a;
     return b;
+  }
+};
+// Unsigned keys (fkey of floating-point values): MAX / MIN only.
+template <int OP>
+struct Op<OP, uint64_t> {
+  static __device__ __forceinline__ uint64_t apply(uint64_t a, uint64_t b) {
+    if (OP == OP_MAX) return a < b ? b : a;
+    return b < a ? b : a;
+  }
+};
+template <int OP>
+struct Op<OP, uint32_t> {
+  static __device__ __forceinline__ uint32_t apply(uint32_t a, uint32_t b) {
+    if (OP == OP_MAX) return a < b ? b : a;
+    return b < a ? b : a;
   }
 };
 template <int OP>
@@ -118,6 +141,10 @@ __device__ __forceinline__ Pair shfl_down(Pair v, int d) {
   r.i = __shfl_down(v.i, d);
   r.pad = 0;
   return r;
+}
+__device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return (uint32_t)__shfl_down((int)v, d); }
+__device__ __forceinline__ uint64_t shfl_down(uint64_t v, int d) {
+  return (uint64_t)__shfl_down((long long)v, d);
 }
 __device__ __forceinline__ int32_t shfl_up(int32_t v, int d) { return __shfl_up(v, d); }
 __device__ __forceinline__ int64_t shfl_up(int64_t v, int d) { return (int64_t)__shfl_up((long long)v, d); }

@@ -351,14 +351,58 @@ __device__ __forceinline__ void small_fetch(const DevSRoot *__restrict__ sroot, 
 // order; a root whose chunks all lie in this window is then updated plainly,
 // one that spans windows through one native atomic per window, in arrival
 // order, in place of the chunk-level trees.
+// Floating-point MAX / MIN hold the window in LDS as fkey keys, so that the
+// trees compare unsigned integers once per pair instead of re-deriving the
+// order of both operands (the keys order the values totally, -0 < +0).
+template <typename T, int OP>
+struct LdsKey {
+  static constexpr bool on = false;
+  using V = T;
+};
+template <int OP>
+struct LdsKey<double, OP> {
+  static constexpr bool on = OP == OP_MAX || OP == OP_MIN;
+  using V = typename std::conditional<on, uint64_t, double>::type;
+};
+template <int OP>
+struct LdsKey<float, OP> {
+  static constexpr bool on = OP == OP_MAX || OP == OP_MIN;
+  using V = typename std::conditional<on, uint32_t, float>::type;
+};
+template <typename K, typename V>
+__device__ __forceinline__ auto lds_value(V v) {
+  if constexpr (K::on)
+    return fkey_inv(v);
+  else
+    return v;
+}
+template <typename T, typename V>
+__device__ __forceinline__ void win_load_key(V *lds, const T *__restrict__ scr, const uint16_t *__restrict__ lpos,
+                                             const DevSWin &w, int bs) {
+  const T *src = scr + (int64_t)w.base * bs;
+  if (bs == 1) {
+#pragma unroll 8
+    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q] & 0x3fff] = fkey(src[q]);
+  } else {
+    const int items = w.n * bs;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < items; q += kStageThreads) {
+      const int k = q / bs;
+      lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)] = fkey(src[q]);
+    }
+  }
+}
+
 template <typename T, int OP, bool ATOM>
 __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot,
                                                const DevWChunk *__restrict__ wchunk,
                                                const uint16_t *__restrict__ lpos, const T *__restrict__ scr,
                                                T *__restrict__ lvl_out, T *__restrict__ root, int bs, int cd_off,
                                                int cv_off) {
+  using K = LdsKey<T, OP>;
+  using V = typename K::V;  // what the LDS holds: the values, or their keys
   extern __shared__ __align__(16) unsigned char smem[];
-  T *lds = reinterpret_cast<T *>(smem);
+  V *lds = reinterpret_cast<V *>(smem);
   DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
   T *cv = reinterpret_cast<T *>(smem + cv_off);
   const DevSWin win = wins[blockIdx.x];
@@ -368,7 +412,10 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
   T rv[kSmallU];
   small_fetch(sroot, root, win, threadIdx.x, nsmall, bs, sd, rv);
   for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
-  win_load(lds, scr, lpos, win, bs);
+  if constexpr (K::on)
+    win_load_key(lds, scr, lpos, win, bs);
+  else
+    win_load(lds, scr, lpos, win, bs);
   __syncthreads();
   for (int q0 = threadIdx.x;;) {
 #pragma unroll
@@ -376,8 +423,8 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
       const int q = q0 + u * kStageThreads;
       if (q >= nsmall) continue;
       const int c = q % bs;
-      const T v = small_tree<T, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
-      st(root + (int64_t)sd[u].root * bs + c, Op<OP, T>::apply(rv[u], v));
+      const V v = small_tree<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
+      st(root + (int64_t)sd[u].root * bs + c, Op<OP, T>::apply(rv[u], lds_value<K>(v)));
       __builtin_amdgcn_sched_barrier(0);  // one tree's registers at a time
     }
     q0 += kSmallU * kStageThreads;
@@ -393,7 +440,7 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
     const int o = wc_off(onf) + lane * LPT;
     const int m = n - lane * LPT;
     for (int c = 0; c < bs; c++) {
-      T x[LPT];
+      V x[LPT];
 #pragma unroll
       for (int s = 0; s < LPT; s++)
         if (s < m) x[s] = ld(lds + (o + s) * bs + c);
@@ -401,14 +448,14 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
       for (int d = 1; d < LPT; d *= 2)
 #pragma unroll
         for (int p = 0; p + d < LPT; p += 2 * d)
-          if (p + d < m) x[p] = Op<OP, T>::apply(x[p], x[p + d]);
-      T v = x[0];
+          if (p + d < m) x[p] = Op<OP, V>::apply(x[p], x[p + d]);
+      V v = x[0];
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
-        const T o2 = shfl_down(v, d);
-        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < n) v = Op<OP, T>::apply(v, o2);
+        const V o2 = shfl_down(v, d);
+        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < n) v = Op<OP, V>::apply(v, o2);
       }
-      if (lane == 0) st(cv + j * bs + c, v);
+      if (lane == 0) st(cv + j * bs + c, (T)lds_value<K>(v));
     }
   }
   __syncthreads();

@@ -192,3 +192,21 @@ def test_partitioned_plan_self_checks(case):
         g = inputs.Graph(2, np.full(n, 1, np.int64), None, np.zeros(n, np.int64), n)
     sf = create(g.nroots, g.iroot, g.ilocal, g.ranks).setup(partition="on", analyze_only=True)
     assert sf.info()["nleaves"] == g.nleaves
+
+
+def test_index_width_limits():
+    """Device indices are int32 (nroots, leaf space < 2^31): larger SFs are
+    rejected at create with SF_ERR_ARG before anything is allocated."""
+    L = S.lib()
+    h = ctypes.c_void_p()
+    nodes = np.zeros((1, 2), np.int64)
+    p = nodes.ctypes.data_as(ctypes.c_void_p)
+    assert L.sf_create(2**31, 1, None, S.SF_COPY_VALUES, p, S.SF_COPY_VALUES, ctypes.byref(h)) == -1
+    assert L.sf_create(1, 2**31, None, S.SF_COPY_VALUES, p, S.SF_COPY_VALUES, ctypes.byref(h)) == -1
+    big = np.array([2**31 - 1], np.int64)
+    assert L.sf_create(1, 1, big.ctypes.data_as(ctypes.c_void_p), S.SF_COPY_VALUES, p, S.SF_COPY_VALUES,
+                       ctypes.byref(h)) == -1
+    ok = np.array([2**20], np.int64)   # a large slot inside the limit is accepted
+    assert L.sf_create(1, 1, ok.ctypes.data_as(ctypes.c_void_p), S.SF_COPY_VALUES, p, S.SF_COPY_VALUES,
+                       ctypes.byref(h)) == 0
+    assert L.sf_destroy(ctypes.byref(h)) == 0
