@@ -12,10 +12,12 @@ already resident in HBM.
 value = algorithmic bytes of a step (unit data + indices; roots counted once
 per distinct touched root) / measured time of a step, in GB/s.
 
-The remaining rows are measured after the timed loop and reported beside it:
-the 3-D halo pattern path vs the generic index path, the batched persistent
-launch vs per-SF launches (eager and graph-replayed), and the differentiable
-gather/scatter chain.  ``--profile-op NAME`` runs a single op (for rocprofv3).
+Unless ``--no-rows`` is given, more is measured after the timed loop and
+reported beside it: each op after a cache-evicting write, a device copy
+ceiling, the direct atomic kernels (partitioning off), the 3-D halo pattern
+path vs the generic index path, the batched persistent launch vs per-SF
+launches (eager and graph-replayed), and the differentiable gather/scatter
+chain.  ``--profile-op NAME`` runs single ops (for rocprofv3 counters).
 """
 import argparse
 import json
@@ -65,7 +67,9 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-rows", action="store_true", help="skip the halo / batch / autograd rows")
+    p.add_argument("--no-rows", action="store_true",
+                   help="time the step only: skip cold-cache times, copy ceiling, direct atomic and halo / batch / "
+                        "autograd rows")
     p.add_argument("--only-row", default=None, choices=["halo", "batch", "autograd"],
                    help="run one row alone (for a profiler) and print its JSON")
     p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
@@ -450,14 +454,6 @@ def main():
                 "frac": round(dom.nbytes / avg_ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.name),
                 "alg_bytes_per_launch": dom.nbytes,
                 "avg_launch_us": round(avg_ms * 1e3, 1)}
-    # the direct persistent atomic kernels, timed alone after the step
-    time_ops(torch, direct, max(5, args.steps // 2), 2)
-    direct_row = {}
-    for o in direct:
-        med = float(np.median(o.times))
-        direct_row[o.name] = {"us": round(med * 1e3, 1), "GBps": round(o.nbytes / med / 1e6, 1),
-                              "kernel": o.kernels, "traffic": measured_traffic(o.name)}
-        log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
     out = {"metric": "effective HBM GB/s (unit data + indices) for SFBcast/SFReduce vs peak; batched vs per-SF time",
            "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -465,10 +461,21 @@ def main():
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
                       "parallelism": "single-gpu"},
-           "ops": per_op, "roofline": roofline, "row_direct_atomic": direct_row,
-           "ops_cold_cache": cold_ops(torch, ops),
-           "copy_ceiling_GBps": copy_ceiling(torch)}
+           "ops": per_op, "roofline": roofline}
     if not args.no_rows:
+        # beside the step (after it, so that a profile of `--no-rows` sees the
+        # step's kernels only): cold-cache op times, a copy ceiling, the direct
+        # atomic kernels, and the halo / batch / autograd rows
+        out["ops_cold_cache"] = cold_ops(torch, ops)
+        out["copy_ceiling_GBps"] = copy_ceiling(torch)
+        time_ops(torch, direct, max(5, args.steps // 2), 2)
+        direct_row = {}
+        for o in direct:
+            med = float(np.median(o.times))
+            direct_row[o.name] = {"us": round(med * 1e3, 1), "GBps": round(o.nbytes / med / 1e6, 1),
+                                  "kernel": o.kernels, "traffic": measured_traffic(o.name)}
+            log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
+        out["row_direct_atomic"] = direct_row
         for name, fn in (("halo", halo_row), ("batch", batch_row), ("autograd", autograd_row)):
             try:
                 out[f"row_{name}"] = fn(torch, S, inputs, args.steps)

@@ -126,11 +126,11 @@ struct HostPlan {
     std::vector<DevSWin> win;
     std::vector<DevSRoot> sroot;      // whole roots, window-major (by degree class inside a window)
     std::vector<DevWChunk> wchunk;    // chunks of large roots, window-major, in chunk order
-    std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start
-                                      //     (< 2^14) | 0x8000 in a run of a root that spans
-                                      //     windows | 0x4000 if that run continues into the next
+    std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start (< 2^14)
     std::vector<uint16_t> pa_loc;     // [L] pass-A tile-major, by increasing scratch slot in a tile: the
-                                      //     tile-local processing offset of that leaf | 0x8000 at a run start
+                                      //     tile-local processing offset of that leaf (13 bits) | 0x8000 at
+                                      //     a run start | 0x2000 if the slot lies in a run of a root that
+                                      //     spans windows | 0x4000 if that run continues into the next
     std::vector<int32_t> pa_run;      // per run of consecutive slots: first slot minus its tile position
     std::vector<int32_t> pa_run0;     // [ntiles + 1] first run of each tile
     std::vector<int32_t> pa_runw;     // per run: its window

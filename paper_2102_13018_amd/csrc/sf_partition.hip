@@ -35,7 +35,8 @@ namespace sfi {
 // ballot; one wavefront turns the group counts into exclusive prefixes; the
 // moves follow.  The tile's run offsets are staged in LDS after the tile's
 // units (byte offset run_off) when the tile has at most run_cap runs.
-constexpr int kMoveGroups = 0x8000 / 64;  // most groups of 64 positions in a tile
+constexpr int kMoveTile = 0x2000;          // most positions in a tile (13-bit offsets in pa_loc)
+constexpr int kMoveGroups = kMoveTile / 64;  // most groups of 64 positions in a tile
 // dynamic LDS of a pass-A/C block when two / one of them share a CU (a CU
 // has 160 KB; the group counts take the rest)
 constexpr size_t kMoveLdsTwo = 80 * 1024 - kMoveGroups * 4 - 512;
@@ -54,11 +55,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 
 // Pass C of the deterministic FetchAndOp adds, to every element of a slot
-// in a run of a root that spans windows (0x8000 in lpos), that run's base:
-// rbase[(2 * window + which) * W + element], which = bit 14 of lpos, window
-// = the window of the slot's pass-C run (staged in LDS beside the run
-// offsets).  FIX is the element size (4 or 8 bytes, integer units; one Word
-// per element) or 0 for a plain move.
+// in a run of a root that spans windows (0x2000 in the slot's pa_loc), that
+// run's base: rbase[(2 * window + which) * W + element], which = bit 14 of
+// pa_loc, window = the window of the slot's pass-C run (staged in LDS beside
+// the run offsets).  FIX is the element size (4 or 8 bytes, integer units;
+// one Word per element) or 0 for a plain move.
 template <int FIX, typename Word>
 __device__ __forceinline__ Word add_word(Word v, Word b) {
   if constexpr (FIX == 4) {
@@ -77,19 +78,16 @@ __device__ __forceinline__ Word add_base(Word v, const void *rbase, int64_t e) {
 }
 
 struct MoveFix {
-  const uint16_t *lpos;
   const int32_t *pa_runw;
   const void *rbase;
 };
 
+#define SP_MOVE_ARGS                                                                                      \
+  const uint16_t *__restrict__ pa_loc, const int32_t *__restrict__ pa_run0, const int32_t *__restrict__ pa_run, \
+      const int32_t *__restrict__ tile_leaf0, const int32_t *__restrict__ pa_slot, int64_t L, int ta,           \
+      Word *__restrict__ leaf, Word *__restrict__ scratch, int W, int run_off, int run_cap, MoveFix fx
 template <typename Word, int DIR, int P, int FIX>
-__global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__restrict__ pa_loc,
-                                                           const int32_t *__restrict__ pa_run0,
-                                                           const int32_t *__restrict__ pa_run,
-                                                           const int32_t *__restrict__ tile_leaf0,
-                                                           const int32_t *__restrict__ pa_slot, int64_t L, int ta,
-                                                           Word *__restrict__ leaf, Word *__restrict__ scratch,
-                                                           int W, int run_off, int run_cap, MoveFix fx) {
+__device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t grp[kMoveGroups];
   Word *lds = reinterpret_cast<Word *>(smem);
@@ -172,15 +170,12 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
   int64_t fes[FIX ? P : 1];
   Word fb[FIX ? P : 1];
   if constexpr (FIX != 0) {
-    int lp[P];
-#pragma unroll
-    for (int k = 0; k < P; k++) lp[k] = (sl[k] >= 0 && sl[k] < L) ? (int)fx.lpos[sl[k]] : 0;
 #pragma unroll
     for (int k = 0; k < P; k++) {
       fes[k] = -1;
-      if (lp[k] & 0x8000) {
+      if (sl[k] >= 0 && (lv[k] & 0x2000)) {
         const int w = use_rl ? rw[rr[k]] : fx.pa_runw[pa_run0[tile] + rr[k]];
-        fes[k] = (int64_t)(2 * w + ((lp[k] >> 14) & 1)) * W;
+        fes[k] = (int64_t)(2 * w + ((lv[k] >> 14) & 1)) * W;
       }
     }
     if (W == 1) {
@@ -194,7 +189,7 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
     const int64_t slot = sl[k];
     if (slot < 0 || slot >= L) continue;
     const int64_t s = slot * W;
-    const int src = (lv[k] & 0x7fff);
+    const int src = (lv[k] & 0x1fff);
     int64_t fe = -1;  // FIX: first rbase element of the slot's run, if it has one
     if constexpr (FIX != 0) fe = fes[k];
     if constexpr (FIX != 0) {
@@ -236,6 +231,20 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(const uint16_t *__res
     for (int q = threadIdx.x; q < items; q += kStageThreads) leaf[l0 + q] = lds[q];
   }
 }
+
+// Tiles of units up to 8 bytes take 64 KB of LDS; two blocks share a CU
+// when the kernel also stays within 64 VGPRs (8 waves per SIMD).
+template <typename Word, int DIR, int P, int FIX>
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sp_move2(SP_MOVE_ARGS) {
+  sp_move_body<Word, DIR, P, FIX>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
+                                  run_cap, fx);
+}
+template <typename Word, int DIR, int P, int FIX>
+__global__ __launch_bounds__(kStageThreads) void k_sp_move(SP_MOVE_ARGS) {
+  sp_move_body<Word, DIR, P, FIX>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
+                                  run_cap, fx);
+}
+#undef SP_MOVE_ARGS
 
 // Load one window from scratch into LDS in root-sorted order (LDS offset =
 // sorted position - window start, the low 14 bits of lpos), and store it
@@ -720,11 +729,19 @@ static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStr
   const unsigned g = (unsigned)hs.tile_leaf0.size();
   const size_t tile = ((size_t)hs.ta * W * sizeof(Word) + 15) / 16 * 16;
   const size_t runs = (size_t)hs.maxrun * sizeof(int32_t) * (FIX ? 2 : 1);  // offsets (and windows)
-  // stage the run offsets in LDS when they fit beside the tile (LDS of a CU
-  // less the static group counts), keeping two tiles per CU where a tile
-  // alone would allow it
-  const size_t room = (tile <= kMoveLdsTwo ? kMoveLdsTwo : kMoveLdsOne) - tile;
-  const int run_cap = runs <= room ? hs.maxrun : 0;
+  // The run tables go to LDS beside the tile when they fit: in half of a
+  // CU's LDS (less the static group counts) two blocks share the CU (the
+  // 64-VGPR build), else in all of it; otherwise they are read from memory.
+  if (tile + runs <= kMoveLdsTwo) {
+    const size_t lds = tile + runs;
+    int rc = allow_lds((const void *)&k_sp_move2<Word, DIR, P, FIX>, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_sp_move2<Word, DIR, P, FIX>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
+                       ds.pa_run0, ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
+                       (Word *)scratch, W, (int)tile, hs.maxrun, fx);
+    return SF_OK;
+  }
+  const int run_cap = tile + runs <= kMoveLdsOne ? hs.maxrun : 0;
   const size_t lds = tile + (run_cap ? runs : 0);
   int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX>, lds);
   if (rc) return rc;
@@ -735,10 +752,9 @@ static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStr
 }
 template <typename Word, int DIR, int FIX = 0>
 static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx = MoveFix{}) {
-  const int ta = sf->hp.sp[cls].ta;  // positions per thread: ta / kStageThreads, at most 32
-  if (ta <= 8 * kStageThreads) return sp_move_p<Word, DIR, 8, FIX>(sf, cls, leaf, scratch, W, st, fx);
-  if (ta <= 16 * kStageThreads) return sp_move_p<Word, DIR, 16, FIX>(sf, cls, leaf, scratch, W, st, fx);
-  return sp_move_p<Word, DIR, 32, FIX>(sf, cls, leaf, scratch, W, st, fx);
+  static_assert(kMoveTile == 8 * kStageThreads, "positions per thread");
+  if (sf->hp.sp[cls].ta > kMoveTile) return SF_ERR_ARG;
+  return sp_move_p<Word, DIR, kMoveTile / kStageThreads, FIX>(sf, cls, leaf, scratch, W, st, fx);
 }
 
 static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_t ub, hipStream_t st) {
@@ -863,7 +879,7 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
                          st, ds.span_first, ds.span_slot, ds.span_root, nspan, (const T *)rtot, rbase, root, bs);
     // pass C with the run bases added: one word per element
     using EW = typename std::conditional<sizeof(T) == 4, uint32_t, uint2>::type;
-    const MoveFix fx{ds.lpos, ds.pa_runw, rbase};
+    const MoveFix fx{ds.pa_runw, rbase};
     rc = sp_move_w<EW, 1, (int)sizeof(T)>(sf, cls, (void *)upd, scr, bs, st, fx);
     if (rc) return rc;
     return sp_check();

@@ -222,9 +222,10 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   // Runs of a large root's chunks inside a window that are not the whole root
   // span windows.  Such a run starts at the window's first sorted position
   // (it continues one from the previous window; "which" 0) or ends at its
-  // last (it continues into the next; which 1).  Their slots carry 0x8000 |
-  // which << 14 in lpos, and every spanning root lists its runs
-  // (2 * window + which) in window order.
+  // last (it continues into the next; which 1).  Their slots are marked
+  // (sflag: 1 | which << 1, carried into pa_loc below), and every spanning
+  // root lists its runs (2 * window + which) in window order.
+  std::vector<uint8_t> sflag(L, 0);
   sp.span_first.assign(1, 0);
   for (int64_t w = 0; w < W; w++) {
     const DevSWin &win = sp.win[w];
@@ -240,7 +241,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
         const int32_t which = o0 == 0 ? 0 : 1;
         if ((which == 0 && have0) || (which == 1 && o1 != win.n)) return SF_ERR_ARG;
         have0 = have0 || which == 0;
-        for (int32_t o = o0; o < o1; o++) sp.lpos[slot_of_g[win.g0 + o]] |= (uint16_t)(0x8000 | (which << 14));
+        for (int32_t o = o0; o < o1; o++) sflag[slot_of_g[win.g0 + o]] = (uint8_t)(1 | (which << 1));
         if (sp.span_root.empty() || sp.span_root.back() != c0.root) {
           if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
           sp.span_root.push_back(c0.root);
@@ -253,7 +254,7 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
   // pass-A tiles: increasing scratch slot inside each tile
   const int64_t ntiles = (L + ta - 1) / ta;
-  if (ta > 0x8000) return SF_ERR_ARG;  // tile offsets take 15 bits
+  if (ta > 0x2000) return SF_ERR_ARG;  // tile offsets take 13 bits
   sp.pa_loc.resize(L);
   sp.pa_run0.assign(ntiles + 1, 0);
   sp.tile_leaf0.assign(ntiles, -1);
@@ -283,8 +284,9 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     }
     for (int64_t at = 0; at < n; at++) {
       if (at > 0 && tdst[at] <= tdst[at - 1]) return SF_ERR_ARG;
+      sp.pa_loc[p0 + at] |= (uint16_t)(sflag[tdst[at]] << 13);  // spanning run, which
       // a new run of consecutive slots, also where the window changes
-      const int32_t w_at = wofp[p0 + sp.pa_loc[p0 + at]];
+      const int32_t w_at = wofp[p0 + (sp.pa_loc[p0 + at] & 0x1fff)];
       if (at == 0 || tdst[at] != tdst[at - 1] + 1 || w_at != sp.pa_runw.back()) {
         sp.pa_loc[p0 + at] |= 0x8000;
         sp.pa_run.push_back(tdst[at] - (int32_t)at);
@@ -308,13 +310,17 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
 
 // Window and tile sizes per unit-size class (overridable for tuning sweeps).
 static void stage_sizes(int cls, int32_t *ta, int32_t *cap) {
+  // 8192 units both ways: two 64 KB pass-A tiles (units <= 8 B) share a CU,
+  // and one 8192-unit window fills a pass-B block (measured best on
+  // spmv_ghost; 4096 and 16384 are slower).  Tiles take at most 8192
+  // positions (13-bit offsets in pa_loc).
   const int64_t ub = cls == 0 ? 8 : 16;
-  *ta = (int32_t)(kStageMaxLds / ub);
-  *cap = cls == 0 ? 8192 : 8192;
+  *ta = 8192;
+  *cap = 8192;
   if (const char *e = getenv(cls == 0 ? "SF_SP0_CAP" : "SF_SP1_CAP")) *cap = atoi(e);
   if (const char *e = getenv(cls == 0 ? "SF_SP0_TA" : "SF_SP1_TA")) *ta = atoi(e);
   *cap = std::max<int32_t>(kChunk, std::min<int32_t>(*cap, (int32_t)(kStageMaxLds / ub)));
-  *ta = std::max<int32_t>(256, std::min<int32_t>(*ta, (int32_t)(kStageMaxLds / ub)));
+  *ta = std::max<int32_t>(256, std::min<int32_t>(*ta, std::min<int32_t>(0x2000, (int32_t)(kStageMaxLds / ub))));
 }
 
 int analyze(sf_s *sf) {
