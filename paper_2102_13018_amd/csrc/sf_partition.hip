@@ -167,7 +167,7 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
   }
   // FIX: the first rbase element of each slot's run (-1: none), and for
   // one-word units the base itself, loaded together ahead of the moves
-  int64_t fes[FIX ? P : 1];
+  int32_t fes[FIX ? P : 1];  // < 2 * windows * W
   Word fb[FIX ? P : 1];
   if constexpr (FIX != 0) {
 #pragma unroll
@@ -175,7 +175,7 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
       fes[k] = -1;
       if (sl[k] >= 0 && (lv[k] & 0x2000)) {
         const int w = use_rl ? rw[rr[k]] : fx.pa_runw[pa_run0[tile] + rr[k]];
-        fes[k] = (int64_t)(2 * w + ((lv[k] >> 14) & 1)) * W;
+        fes[k] = (2 * w + ((lv[k] >> 14) & 1)) * W;
       }
     }
     if (W == 1) {
@@ -850,6 +850,7 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
   const DevPlan::Stage &ds = d.sp[cls];
   const unsigned gw = (unsigned)hs.win.size();
   const bool det = !atomic && std::is_integral<T>::value;  // floating point: atomic only
+  if (det && (int64_t)2 * gw * bs >= INT32_MAX) return SF_ERR_UNSUPPORTED;  // 32-bit run-base index
   // scratch: window-major leaf units, then run totals and run bases (2 per window)
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
   const size_t runs_bytes = ((size_t)2 * gw * ub + 255) / 256 * 256;

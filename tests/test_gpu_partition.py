@@ -266,3 +266,23 @@ def test_partition_atomic_single_root():
     ones = np.ones(n, np.int64)
     r, u = run_fetch_mode(g1, root, ones, np.zeros(n, np.int64), "atomic")
     check_fetch_chain(g1.iroot, np.arange(n), root, ones, u, r)
+
+
+@pytest.mark.parametrize("dtype,bs", [(np.int32, 2), (np.int32, 3), (np.int64, 2)])
+def test_partition_fetch_units(zipf, dtype, bs):
+    """FetchAndOp on multi-element units through both unit-size classes
+    (8 and 12 / 16 bytes): deterministic bit-exact, atomic a valid chain
+    per element."""
+    from helpers import check_fetch_chain
+    g = zipf
+    rng = np.random.default_rng(815 + bs)
+    root0 = rng.integers(0, 100, (g.nroots, bs)).astype(dtype)
+    leaf = rng.integers(0, 100, (g.nleaves, bs)).astype(dtype)
+    upd0 = np.zeros((g.nleaves, bs), dtype)
+    wr, wu = oracle.fetch_and_op(g.nroots, g.iroot, None, root0, leaf, upd0)
+    r, u = run_fetch_mode(g, root0, leaf, upd0, "deterministic")
+    check(r, wr, f"fetch det roots bs {bs}")
+    check(u, wu, f"fetch det leafupdate bs {bs}")
+    r, u = run_fetch_mode(g, root0, leaf, upd0, "atomic")
+    for c in range(bs):
+        check_fetch_chain(g.iroot, np.arange(g.nleaves), root0[:, c], leaf[:, c], u[:, c], r[:, c])
