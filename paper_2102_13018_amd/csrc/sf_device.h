@@ -155,6 +155,37 @@ __device__ __forceinline__ int64_t shfl_idx(int64_t v, int l) { return (int64_t)
 __device__ __forceinline__ double shfl_idx(double v, int l) { return __shfl(v, l); }
 __device__ __forceinline__ float shfl_idx(float v, int l) { return __shfl(v, l); }
 
+// Streaming (non-temporal) accesses for data used once, so that it does not
+// displace reused lines from the caches.  Vector words go through the
+// matching native vector type.
+template <typename T>
+struct NtWord {
+  using type = T;
+};
+template <>
+struct NtWord<uint2> {
+  typedef unsigned int type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct NtWord<uint4> {
+  typedef unsigned int type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NtWord<Pair> {  // 16 bytes, 16-byte aligned in the buffers it streams
+  typedef unsigned int type __attribute__((ext_vector_type(4)));
+};
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  using N = typename NtWord<T>::type;
+  const N v = __builtin_nontemporal_load(reinterpret_cast<const N *>(p));
+  return *reinterpret_cast<const T *>(&v);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+  using N = typename NtWord<T>::type;
+  __builtin_nontemporal_store(*reinterpret_cast<const N *>(&v), reinterpret_cast<N *>(p));
+}
+
 // Index of the t-th leaf of a segment side with a pattern (Section 5.2).
 __device__ __forceinline__ int32_t pat_index(const DevPattern &p, int32_t t) {
   if (p.kind == SF_PATTERN_CONTIGUOUS) return p.start + t;

@@ -46,15 +46,16 @@ __global__ __launch_bounds__(kBlock) void k_bcast_move(const DevSegment *__restr
       if (q < items) {
         const int t = tl.t0 + q / w;
         const int c = q % w;
-        const int32_t r = seg_root(sg, ridx, t);
-        const int32_t l = seg_leaf(sg, lidx, t);
+        // indices and leaf writes stream (used once); root reads stay cached
+        const int32_t r = sg.root.kind == SF_PATTERN_GENERIC ? ld_stream(ridx + sg.roff + t) : pat_index(sg.root, t);
+        const int32_t l = sg.leaf.kind == SF_PATTERN_GENERIC ? ld_stream(lidx + sg.loff + t) : pat_index(sg.leaf, t);
         v[u] = root[(int64_t)r * w + c];
         dst[u] = (int64_t)l * w + c;
       }
     }
 #pragma unroll
     for (int u = 0; u < U; u++)
-      if (dst[u] >= 0) leaf[dst[u]] = v[u];
+      if (dst[u] >= 0) st_stream(leaf + dst[u], v[u]);
   }
 }
 

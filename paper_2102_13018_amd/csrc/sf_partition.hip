@@ -115,9 +115,9 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
     if constexpr (FIX != 0)
       for (int i = threadIdx.x; i < nrun; i += kStageThreads) rw[i] = fx.pa_runw[pa_run0[tile] + i];
   }
-  if (DIR == 0 && leaf0 >= 0) {
+  if (DIR == 0 && leaf0 >= 0) {  // leaf units are read once: streaming loads
 #pragma unroll 8
-    for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = leaf[l0 + q];
+    for (int q = threadIdx.x; q < items; q += kStageThreads) lds[q] = ld_stream(leaf + l0 + q);
   }
   // run starts per group of 64 positions (group of position jj: jj >> 6)
 #pragma unroll
@@ -225,10 +225,10 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
       }
     }
   }
-  if (DIR == 1 && leaf0 >= 0) {
+  if (DIR == 1 && leaf0 >= 0) {  // leaf units are written once: streaming stores
     __syncthreads();
 #pragma unroll 8
-    for (int q = threadIdx.x; q < items; q += kStageThreads) leaf[l0 + q] = lds[q];
+    for (int q = threadIdx.x; q < items; q += kStageThreads) st_stream(leaf + l0 + q, lds[q]);
   }
 }
 
@@ -253,16 +253,16 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_move(SP_MOVE_ARGS) {
 template <typename T>
 __device__ __forceinline__ void win_load(T *lds, const T *__restrict__ scr, const uint16_t *__restrict__ lpos,
                                          const DevSWin &w, int bs) {
-  const T *src = scr + (int64_t)w.base * bs;
+  const T *src = scr + (int64_t)w.base * bs;  // read once: streaming loads
   if (bs == 1) {
 #pragma unroll 8
-    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q] & 0x3fff] = src[q];
+    for (int q = threadIdx.x; q < w.n; q += kStageThreads) lds[lpos[w.base + q] & 0x3fff] = ld_stream(src + q);
   } else {
     const int items = w.n * bs;
 #pragma unroll 4
     for (int q = threadIdx.x; q < items; q += kStageThreads) {
       const int k = q / bs;
-      lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)] = src[q];
+      lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)] = ld_stream(src + q);
     }
   }
 }
