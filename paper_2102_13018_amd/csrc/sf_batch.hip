@@ -67,15 +67,15 @@ __device__ __forceinline__ void bw_move(const BatchItemDev &it, const BatchTile 
         const int lt = fdiv(q, it.magic_words);
         const int c = q - lt * w;
         const int t = bt.t0 + lt;
-        const int32_t r = seg_root(sg, it.ridx, t);
-        const int32_t l = seg_leaf(sg, it.lidx, t);
+        const int32_t r = seg_root_s(sg, it.ridx, t);  // indices and leaf writes stream
+        const int32_t l = seg_leaf_s(sg, it.lidx, t);
         v[u] = root[(int64_t)r * w + c];
         dst[u] = (int64_t)l * w + c;
       }
     }
 #pragma unroll
     for (int u = 0; u < LPT; u++)
-      if (dst[u] >= 0) leaf[dst[u]] = v[u];
+      if (dst[u] >= 0) st_stream(leaf + dst[u], v[u]);
   }
 }
 
@@ -97,9 +97,9 @@ __device__ __forceinline__ void bw_red_atomic(const BatchItemDev &it, const Batc
         const int lt = fdiv(q, it.magic_bs);
         const int c = q - lt * bs;
         const int t = bt.t0 + lt;
-        const int32_t r = seg_root(sg, it.ridx, t);
-        const int32_t l = seg_leaf(sg, it.lidx, t);
-        v[u] = leaf[(int64_t)l * bs + c];
+        const int32_t r = seg_root_s(sg, it.ridx, t);  // indices and leaf reads stream
+        const int32_t l = seg_leaf_s(sg, it.lidx, t);
+        v[u] = ld_stream(leaf + (int64_t)l * bs + c);
         dst[u] = (int64_t)r * bs + c;
       }
     }
@@ -134,7 +134,7 @@ __device__ __forceinline__ void bw_det_class(const BatchItemDev &it, const Batch
     Vec<T, NV> x[D];
 #pragma unroll
     for (int p = 0; p < D; p++)
-      if (p < n) x[p] = vld<T, NV>(leaf + (int64_t)it.sl[g0 + p] * bs + c);
+      if (p < n) x[p] = ld_stream(reinterpret_cast<const Vec<T, NV> *>(leaf + (int64_t)ld_stream(it.sl + g0 + p) * bs + c));
 #pragma unroll
     for (int d = 1; d < D; d *= 2)
 #pragma unroll
@@ -173,7 +173,7 @@ __device__ __forceinline__ void bw_det_wave(const BatchItemDev &it, const BatchT
       T x[LPT];
 #pragma unroll
       for (int s = 0; s < LPT; s++)
-        if (s < m) x[s] = leaf[(int64_t)it.sl[g0 + lane * LPT + s] * bs + c];
+        if (s < m) x[s] = ld_stream(leaf + (int64_t)ld_stream(it.sl + g0 + lane * LPT + s) * bs + c);
 #pragma unroll
       for (int d = 1; d < LPT; d *= 2)
 #pragma unroll

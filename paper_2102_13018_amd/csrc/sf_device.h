@@ -156,34 +156,37 @@ __device__ __forceinline__ double shfl_idx(double v, int l) { return __shfl(v, l
 __device__ __forceinline__ float shfl_idx(float v, int l) { return __shfl(v, l); }
 
 // Streaming (non-temporal) accesses for data used once, so that it does not
-// displace reused lines from the caches.  Vector words go through the
-// matching native vector type.
-template <typename T>
-struct NtWord {
-  using type = T;
+// displace reused lines from the caches.  Values of 4, 8 and 16 bytes go
+// through the native integer vector of that size (aligned to it in the
+// buffers they stream).
+template <int BYTES>
+struct NtBytes;
+template <>
+struct NtBytes<4> {
+  typedef unsigned int type;
 };
 template <>
-struct NtWord<uint2> {
+struct NtBytes<8> {
   typedef unsigned int type __attribute__((ext_vector_type(2)));
 };
 template <>
-struct NtWord<uint4> {
-  typedef unsigned int type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct NtWord<Pair> {  // 16 bytes, 16-byte aligned in the buffers it streams
+struct NtBytes<16> {
   typedef unsigned int type __attribute__((ext_vector_type(4)));
 };
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p) {
-  using N = typename NtWord<T>::type;
+  using N = typename NtBytes<sizeof(T)>::type;
   const N v = __builtin_nontemporal_load(reinterpret_cast<const N *>(p));
-  return *reinterpret_cast<const T *>(&v);
+  T r;
+  __builtin_memcpy(&r, &v, sizeof(T));
+  return r;
 }
 template <typename T>
 __device__ __forceinline__ void st_stream(T *p, T v) {
-  using N = typename NtWord<T>::type;
-  __builtin_nontemporal_store(*reinterpret_cast<const N *>(&v), reinterpret_cast<N *>(p));
+  using N = typename NtBytes<sizeof(T)>::type;
+  N w;
+  __builtin_memcpy(&w, &v, sizeof(T));
+  __builtin_nontemporal_store(w, reinterpret_cast<N *>(p));
 }
 
 // Index of the t-th leaf of a segment side with a pattern (Section 5.2).
@@ -202,6 +205,13 @@ __device__ __forceinline__ int32_t seg_root(const DevSegment &s, const int32_t *
 }
 __device__ __forceinline__ int32_t seg_leaf(const DevSegment &s, const int32_t *__restrict__ lidx, int32_t t) {
   return s.leaf.kind == SF_PATTERN_GENERIC ? lidx[s.loff + t] : pat_index(s.leaf, t);
+}
+// The same, for index arrays read once per operation (streaming loads).
+__device__ __forceinline__ int32_t seg_root_s(const DevSegment &s, const int32_t *__restrict__ ridx, int32_t t) {
+  return s.root.kind == SF_PATTERN_GENERIC ? ld_stream(ridx + s.roff + t) : pat_index(s.root, t);
+}
+__device__ __forceinline__ int32_t seg_leaf_s(const DevSegment &s, const int32_t *__restrict__ lidx, int32_t t) {
+  return s.leaf.kind == SF_PATTERN_GENERIC ? ld_stream(lidx + s.loff + t) : pat_index(s.leaf, t);
 }
 
 // ------------------------------------------------------------- atomics

@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_bcast_move(const DevSegment *__restr
         const int t = tl.t0 + q / w;
         const int c = q % w;
         // indices and leaf writes stream (used once); root reads stay cached
-        const int32_t r = sg.root.kind == SF_PATTERN_GENERIC ? ld_stream(ridx + sg.roff + t) : pat_index(sg.root, t);
-        const int32_t l = sg.leaf.kind == SF_PATTERN_GENERIC ? ld_stream(lidx + sg.loff + t) : pat_index(sg.leaf, t);
+        const int32_t r = seg_root_s(sg, ridx, t);
+        const int32_t l = seg_leaf_s(sg, lidx, t);
         v[u] = root[(int64_t)r * w + c];
         dst[u] = (int64_t)l * w + c;
       }
