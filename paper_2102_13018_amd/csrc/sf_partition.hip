@@ -38,9 +38,9 @@ namespace sfi {
 constexpr int kMoveTile = 0x2000;          // most positions in a tile (13-bit offsets in pa_loc)
 constexpr int kMoveGroups = kMoveTile / 64;  // most groups of 64 positions in a tile
 // dynamic LDS of a pass-A/C block when two / one of them share a CU (a CU
-// has 160 KB; the group counts take the rest)
-constexpr size_t kMoveLdsTwo = 80 * 1024 - kMoveGroups * 4 - 512;
-constexpr size_t kMoveLdsOne = 160 * 1024 - kMoveGroups * 4 - 512;
+// has 160 KB; the static group counts take the rest)
+constexpr size_t kMoveLdsTwo = 80 * 1024 - kMoveGroups * 4;
+constexpr size_t kMoveLdsOne = 160 * 1024 - kMoveGroups * 4;
 
 // Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
 // b % 8), each XCD with its own L2.  Neighbouring tiles write and read the
