@@ -270,6 +270,11 @@ template <typename T>
 __device__ __forceinline__ void win_store(const T *lds, T *__restrict__ scr, const uint16_t *__restrict__ lpos,
                                           const DevSWin &w, int bs) {
   T *dst = scr + (int64_t)w.base * bs;
+  if (bs == 1) {
+#pragma unroll 8
+    for (int q = threadIdx.x; q < w.n; q += kStageThreads) dst[q] = lds[lpos[w.base + q] & 0x3fff];
+    return;
+  }
   const int items = w.n * bs;
 #pragma unroll 4
   for (int q = threadIdx.x; q < items; q += kStageThreads) {
