@@ -16,7 +16,7 @@ namespace sfi {
 
 // ------------------------------------------------------------------ limits
 constexpr int kBlock = 256;          // threads per block of the stream kernels
-constexpr int kTileLeaves = 2048;    // largest work tile of the stream kernels (leaves)
+constexpr int kTileLeaves = 1024;    // largest work tile of the stream kernels (leaves)
 constexpr int kTileMin = 256;        // smallest work tile
 constexpr int kChunkLPT = 4;         // leaves per lane of the wave-chunk reduction
 constexpr int kChunk = 64 * kChunkLPT;  // leaves per aligned chunk (power of two)

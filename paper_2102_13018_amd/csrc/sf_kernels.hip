@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast_move(const DevSegment *__restr
   const DevSegment sg = segs[tl.seg];
   const int w = W > 0 ? W : wrt;
   const int items = (tl.t1 - tl.t0) * w;
-  constexpr int U = 8;  // loads in flight per thread
+  constexpr int U = 4;  // loads in flight per thread (more, smaller blocks measured faster)
   for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * U) {
     Word v[U];
     int64_t dst[U];
