@@ -28,6 +28,11 @@
  *    pointer and returns SF_ERR_ARG for memory that is not device memory.
  *  - Device indices are 32-bit: nroots and the leaf space must be < 2^31.
  *  - An SF and its scratch memory may be used by one stream at a time.
+ *    Scratch is allocated on an operation's first call and grown when a
+ *    later call needs more; outgrown buffers are kept until sf_setup or
+ *    sf_destroy.  So calls may be captured into a HIP graph once the same
+ *    calls have run eagerly (capture allocates nothing), and such graphs
+ *    stay valid until the SF is set up again or destroyed.
  *  - sf_setup uploads the plan to the current device; *_begin returns
  *    SF_ERR_ARG when called with another device current.
  */

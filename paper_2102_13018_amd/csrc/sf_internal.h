@@ -192,9 +192,13 @@ struct sf_s {
   bool has_dup_roots = false;
   int device = -1;
   sfi::DevPlan dp;
-  // scratch for chunk levels / MAXLOC passes, grown on demand
+  // scratch for chunk levels / MAXLOC passes / the partitioned path, grown on
+  // demand; outgrown buffers are kept (retired) until the device plan is
+  // freed, so that work already enqueued or captured into a graph that uses
+  // them stays valid
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  std::vector<void *> retired;
   std::vector<sfi::Pending> pending;
   std::mutex mu;
 };

@@ -553,6 +553,8 @@ int analyze(sf_s *sf) {
 void free_device(sf_s *sf) {
   if (sf->dp.blob) hipFree(sf->dp.blob);
   if (sf->scratch) hipFree(sf->scratch);
+  for (void *p : sf->retired) hipFree(p);
+  sf->retired.clear();
   sf->dp = DevPlan{};
   sf->scratch = nullptr;
   sf->scratch_bytes = 0;
@@ -576,17 +578,12 @@ AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes, int 
 
 int ensure_scratch(sf_s *sf, size_t bytes) {
   if (bytes <= sf->scratch_bytes) return SF_OK;
-  if (sf->scratch) {
-    hipError_t e = hipFree(sf->scratch);
-    sf->scratch = nullptr;
-    sf->scratch_bytes = 0;
-    if (e != hipSuccess) return set_hip_error(e);
-  }
-  hipError_t e = hipMalloc(&sf->scratch, bytes);
-  if (e != hipSuccess) {
-    sf->scratch = nullptr;
-    return e == hipErrorOutOfMemory ? SF_ERR_OOM : set_hip_error(e);
-  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? SF_ERR_OOM : set_hip_error(e);
+  // the outgrown buffer may still be in use by enqueued or captured work
+  if (sf->scratch) sf->retired.push_back(sf->scratch);
+  sf->scratch = p;
   sf->scratch_bytes = bytes;
   return SF_OK;
 }

@@ -286,3 +286,60 @@ def test_partition_fetch_units(zipf, dtype, bs):
     r, u = run_fetch_mode(g, root0, leaf, upd0, "atomic")
     for c in range(bs):
         check_fetch_chain(g.iroot, np.arange(g.nleaves), root0[:, c], leaf[:, c], u[:, c], r[:, c])
+
+
+@pytest.mark.parametrize("mode", ["deterministic", "atomic"])
+def test_partition_graph_capture(zipf, mode):
+    """Partitioned Reduce and FetchAndOp captured into a HIP graph after one
+    eager call of each: three replays, each after eager work that resets the
+    inputs and synchronises; before the second, an eager call with a wider
+    unit grows the SF's scratch (the captured graph keeps its buffer).  Every
+    replay must give the oracle's result (the atomic bar in atomic mode)."""
+    from helpers import atomic_sum_tolerance, check_fetch_chain
+    g = zipf
+    rng = np.random.default_rng(816)
+    sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode=mode, partition="on")
+    leaf = rng.standard_normal(g.nleaves)
+    root0 = rng.standard_normal(g.nroots)
+    want = oracle.reduce(g.nroots, g.iroot, None, leaf, root0, "sum")
+    froot0 = rng.integers(0, 100, g.nroots).astype(np.int64)
+    fleaf = rng.integers(0, 100, g.nleaves).astype(np.int64)
+    fwr, fwu = oracle.fetch_and_op(g.nroots, g.iroot, None, froot0, fleaf, np.zeros(g.nleaves, np.int64))
+    dl, dr0, dr = dev(leaf), dev(root0), dev(root0)
+    dfl, dfr0, dfr, dfu = dev(fleaf), dev(froot0), dev(froot0), dev(np.zeros(g.nleaves, np.int64))
+    u64, ui64 = S.SfUnit(S.SF_F64, 1), S.SfUnit(S.SF_I64, 1)
+
+    def run():
+        sf.reduce(dl, dr, "sum", unit=u64)
+        sf.fetch_and_op(dfr, dfl, dfu, "sum", unit=ui64)
+
+    def check_all(what):
+        r, fr, fu = host(dr, root0), host(dfr, froot0), host(dfu, fleaf)
+        if mode == "deterministic":
+            check(r, want, f"{what}: reduce")
+            check(fr, fwr, f"{what}: fetch roots")
+            check(fu, fwu, f"{what}: fetch leafupdate")
+        else:
+            ok, worst = atomic_sum_tolerance(r, want, root0, leaf, g.iroot, 1e-12)
+            assert ok, f"{what}: reduce {worst:.3g}"
+            check_fetch_chain(g.iroot, np.arange(g.nleaves), froot0, fleaf, fu, fr)
+
+    run()  # eager: allocates scratch, sets kernel attributes
+    torch.cuda.synchronize()
+    check_all("eager")
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        run()
+    wide = rng.standard_normal((g.nleaves, 2))
+    wroot = rng.standard_normal((g.nroots, 2))
+    for rep in range(3):
+        dr.copy_(dr0)
+        dfr.copy_(dfr0)
+        dfu.zero_()
+        if rep == 1:  # grows the scratch: 16-byte units
+            dw, dwr = dev(wide), dev(wroot)
+            sf.reduce(dw, dwr, "sum", unit=S.SfUnit(S.SF_F64, 2))
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        check_all(f"replay {rep}")
