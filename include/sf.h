@@ -248,7 +248,9 @@ int sf_batch_launch_separate(sf_batch_t batch, hipStream_t stream);
 
 /* Capture the batch's launch sequence (mode 0: the single persistent
  * launch, mode 1: one launch per item) into a HIP graph on stream; later
- * sf_batch_graph_launch calls replay it. */
+ * sf_batch_graph_launch calls replay it.  Scratch memory the items need is
+ * allocated before the capture.  sf_batch_set_config and sf_batch_autotune
+ * drop the captured graph (capture again afterwards). */
 int sf_batch_graph_capture(sf_batch_t batch, int32_t mode, hipStream_t stream);
 int sf_batch_graph_launch(sf_batch_t batch, hipStream_t stream);
 

@@ -440,11 +440,13 @@ extern "C" int sf_batch_graph_capture(sf_batch_t b, int32_t mode, hipStream_t st
   if (!b || !stream || (mode != 0 && mode != 1)) return SF_ERR_ARG;
   batch_free_graph(b);
   if (mode == 1) {
-    // the per-item path may grow scratch memory: do that before capturing
+    // the per-item path may grow scratch memory (chunk levels, or the
+    // partitioned path of large SFs): do that before capturing
     for (const sf_batch_item &it : b->items) {
       if (it.kind != SF_KIND_REDUCE || !it.sf->has_dup_roots) continue;
-      const size_t need = 2 * (size_t)std::max<int64_t>(it.sf->hp.scratch_len, 1) * it.unit.bs *
-                          elem_size(it.unit.dtype);
+      const size_t ub = (size_t)it.unit.bs * elem_size(it.unit.dtype);
+      const size_t need = std::max(2 * (size_t)std::max<int64_t>(it.sf->hp.scratch_len, 1) * ub,
+                                   part_scratch_need(it.sf, ub));
       int rc = ensure_scratch(it.sf, need);
       if (rc) return rc;
     }

@@ -438,6 +438,7 @@ namespace sfi {
 // with native atomics where chunks of one root meet, and
 // its unit-size class (0: <= 8 bytes, 1: <= 16 bytes, -1: not staged).
 int stage_class(int64_t unit_bytes);
+size_t part_scratch_need(const sf_s *sf, size_t unit_bytes);
 template <typename T, int OP>
 int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hipStream_t st);
 template <typename T>

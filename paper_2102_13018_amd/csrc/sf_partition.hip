@@ -786,6 +786,18 @@ static PassBLds passb_lds(const HostPlan::Stage &hs, size_t ub) {
   return {(int)cd, (int)cv, cv + (size_t)hs.maxbig * ub};
 }
 
+// Scratch bytes the partitioned Reduce / FetchAndOp of this SF need for a
+// unit of ub bytes (0 when the SF does not take that path).
+size_t part_scratch_need(const sf_s *sf, size_t ub) {
+  const HostPlan &h = sf->hp;
+  const int cls = stage_class((int64_t)ub);
+  if (!h.part || cls < 0) return 0;
+  const size_t main_bytes = ((size_t)sf->nleaves * ub + 255) / 256 * 256;
+  const size_t lvl = (size_t)std::max<int64_t>(h.scratch_len, 1) * ub;
+  const size_t runs = ((size_t)2 * h.sp[cls].win.size() * ub + 255) / 256 * 256;
+  return main_bytes + std::max(2 * lvl, 2 * runs);
+}
+
 template <typename T, int OP, bool ATOM>
 static int sp_reduce_launch(unsigned gw, const PassBLds &pl, int cls, hipStream_t st, const DevSWin *win,
                             const DevSRoot *sroot, const DevWChunk *wchunk, const uint16_t *lpos, const T *scr,

@@ -116,3 +116,37 @@ def test_autotune_candidates_agree(batch_case, tmp_path):
     reset(case)
     batch.launch()
     check(case, "autotuned")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_graph_with_partitioned_item(mode):
+    """A batch holding a large SF that takes the partitioned path (atomic
+    mode) beside a small Bcast, captured before either SF has run: the
+    capture allocates the scratch the per-item launches need beforehand;
+    three replays with eager resets and synchronisation between them."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rng = np.random.default_rng(950 + mode)
+    gz = inputs.spmv_ghost(seed=3, nroots=20000, nleaves=300001)
+    sfz = S.StarForest(gz.nroots, gz.iroot, None, gz.ranks).setup(reduce_mode="atomic", partition="on")
+    rz, lz = rng.standard_normal(gz.nroots), rng.standard_normal(gz.nleaves)
+    wz = oracle.reduce(gz.nroots, gz.iroot, None, lz, rz)
+    gb = inputs.single_sf(seed=951, nroots=3000, nleaves=9000, leafspace=9500)
+    sfb = S.StarForest(gb.nroots, gb.iroot, gb.ilocal, gb.ranks).setup()
+    rb, lb = rng.standard_normal((gb.nroots, 2)), rng.standard_normal((gb.leafspace, 2))
+    wb = oracle.bcast(gb.nroots, gb.iroot, gb.ilocal, rb, lb)
+    t = [torch.from_numpy(a).cuda() for a in (rz, lz, rb, lb)]
+    u1, u2 = S.SfUnit(S.SF_F64, 1), S.SfUnit(S.SF_F64, 2)
+    batch = S.Batch([(sfz, u1, "reduce", "sum", t[0], t[1]), (sfb, u2, "bcast", "replace", t[2], t[3])])
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    batch.graph_capture(mode, stream)
+    for rep in range(3):
+        t[0].copy_(torch.from_numpy(rz))
+        t[3].copy_(torch.from_numpy(lb))
+        torch.cuda.synchronize()
+        batch.graph_launch(stream)
+        stream.synchronize()
+        ok, worst = atomic_sum_tolerance(t[0].cpu().numpy(), wz, rz, lz, gz.iroot, 1e-12)
+        assert ok, f"mode {mode} replay {rep}: partitioned item {worst:.3g}"
+        assert same_bits(t[3].cpu().numpy(), wb), f"mode {mode} replay {rep}: bcast item"
