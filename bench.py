@@ -97,7 +97,8 @@ def build_spmv_ops(torch, S, inputs, g):
     idx = 4 * L                                     # iremote (ilocal is NULL)
     t0 = time.time()
     sf = S.StarForest(R, g.iroot, None, g.ranks).setup(reduce_mode="atomic")
-    log(f"setup of {L} leaves: {time.time() - t0:.2f} s, info {sf.info()}")
+    setup_s = time.time() - t0
+    log(f"setup of {L} leaves: {setup_s:.2f} s, info {sf.info()}")
     # the direct persistent atomic kernels (partitioning off), timed beside the step
     sfd = S.StarForest(R, g.iroot, None, g.ranks).setup(reduce_mode="atomic", partition="off")
 
@@ -152,7 +153,7 @@ def build_spmv_ops(torch, S, inputs, g):
         Op("reduce_max_f64_atomic_direct", red("atomic", xl64, xr64, "max", u64, sfd), r8(8), "k_reduce_atomic"),
         Op("fetch_and_op_i64_atomic_direct", fop("atomic", sfd), f8(8), "k_fop_atomic_hot"),
     ]
-    data = dict(xr64=xr64, xl64=xl64, deg=deg, Rt=Rt)
+    data = dict(xr64=xr64, xl64=xl64, deg=deg, Rt=Rt, setup_s=setup_s)
     return sf, ops, direct, data
 
 
@@ -246,7 +247,19 @@ def cpu_baseline(g, budget_s=12.0):
         rounds += 1
     return {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{rounds} rounds of (" + ", ".join(j[0] for j in jobs) + ") on the full spmv_ghost SF, "
-                      f"sequential C oracle, {tot_t:.1f} s of CPU time"}
+                      f"sequential C oracle, {tot_t:.1f} s of CPU time",
+            "cpu": cpu_model(), "host_threads": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def graph_time_us(torch, fn, reps=20):
@@ -460,7 +473,8 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
-                      "parallelism": "single-gpu"},
+                      "cache": "warm (ops back to back; see ops_cold_cache)",
+                      "setup_s": round(data["setup_s"], 2), "parallelism": "single-gpu"},
            "ops": per_op, "roofline": roofline}
     if not args.no_rows:
         # beside the step (after it, so that a profile of `--no-rows` sees the
@@ -468,6 +482,7 @@ def main():
         # atomic kernels, and the halo / batch / autograd rows
         out["ops_cold_cache"] = cold_ops(torch, ops)
         out["copy_ceiling_GBps"] = copy_ceiling(torch)
+        out["value_vs_copy_ceiling"] = round(value / out["copy_ceiling_GBps"], 4)
         time_ops(torch, direct, max(5, args.steps // 2), 2)
         direct_row = {}
         for o in direct:

@@ -16,6 +16,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <system_error>
+#include <thread>
 
 #include "sf_internal.h"
 
@@ -535,12 +537,28 @@ int analyze(sf_s *sf) {
   if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionMin))) {
     std::vector<int32_t> proc_slot(L);
     for (int64_t p = 0; p < L; p++) proc_slot[p] = (int32_t)slot(proc_leaf[p]);
-    for (int cls = 0; cls < 2; cls++) {
-      int32_t ta, cap;
-      stage_sizes(cls, &ta, &cap);
-      const int rc = build_stage(hp, hp.sp[cls], perm, proc_leaf, proc_slot, L, ta, cap);
-      if (rc) return rc;
+    // the two unit-size classes read the shared plan and write only their
+    // own stage: built side by side
+    int rcs[2] = {SF_OK, SF_OK};
+    auto work = [&](int cls) {
+      try {
+        int32_t ta, cap;
+        stage_sizes(cls, &ta, &cap);
+        rcs[cls] = build_stage(hp, hp.sp[cls], perm, proc_leaf, proc_slot, L, ta, cap);
+      } catch (const std::bad_alloc &) {
+        rcs[cls] = SF_ERR_OOM;
+      }
+    };
+    try {
+      std::thread other(work, 1);
+      work(0);
+      other.join();
+    } catch (const std::system_error &) {  // no thread: one after the other
+      work(0);
+      work(1);
     }
+    for (int rc : rcs)
+      if (rc) return rc;
     hp.part = true;
   }
 
