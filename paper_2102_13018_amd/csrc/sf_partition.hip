@@ -632,31 +632,63 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop(const DevSWin *__restr
       }
     }
     __syncthreads();
-    // 2: per run, chunk offsets inside the run and the run's base
-    for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
-      const int j = q / bs, c = q - j * bs;
-      const int32_t r = cd[j].root;
-      if (j > 0 && cd[j - 1].root == r) continue;  // not the first chunk of its run
-      int j1 = j;
-      T run = T(0);
-      for (; j1 < nb && cd[j1].root == r; j1++) {
-        const T t = cv[j1 * bs + c];
-        cv[j1 * bs + c] = run;
-        run = Op<OP_SUM, T>::apply(run, t);
+    // 2: per run (the chunks of one root in this window), each chunk's
+    // offset inside the run and the run's base: a segmented scan over the
+    // chunk totals, one wavefront per unit component, 64 chunks at a time.
+    // The last lane of a run takes its base (the root value when the window
+    // holds the whole root, else a returning atomic add, or in deterministic
+    // mode 0 with the run total left for the cross-window scan) and the base
+    // is broadcast to the run's chunks; chunks of a run that began in an
+    // earlier group get it once the run ends.
+    for (int c = wv; c < bs; c += kStageThreads / 64) {
+      T carry = T(0);  // running total of a run continuing from the previous group
+      int jh = 0;      // head chunk of that run
+      for (int g = 0; g < nb; g += 64) {
+        const int j = g + lane;
+        const bool in = j < nb;
+        const int32_t r = in ? cd[j].root : -1;
+        const bool head = in && (j == 0 || cd[j - 1].root != r);
+        const bool tail = in && (j == nb - 1 || cd[j + 1].root != r);
+        const T t = in ? cv[j * bs + c] : T(0);
+        const uint64_t hm = __ballot(head), tm = __ballot(tail);
+        const uint64_t le = lane == 63 ? ~0ull : (2ull << lane) - 1;
+        const uint64_t hle = hm & le;
+        const int s0 = hle ? 63 - __clzll(hle) : -1;  // this lane's run head lane, -1: earlier group
+        T v = t;
+#pragma unroll
+        for (int d = 1; d < 64; d *= 2) {
+          const T y = shfl_up(v, d);
+          if (lane - d >= (s0 < 0 ? 0 : s0)) v = Op<OP_SUM, T>::apply(y, v);
+        }
+        if (s0 < 0) v = Op<OP_SUM, T>::apply(carry, v);
+        const T vprev = shfl_up(v, 1);
+        const T ex = head ? T(0) : lane > 0 ? vprev : carry;
+        const int j0 = s0 < 0 ? jh : g + s0;
+        T base = T(0);
+        if (tail) {
+          T *rp = root + (int64_t)r * bs + c;
+          if (wc_first(cd[j0].onf) && wc_last(cd[j].onf)) {
+            base = *rp;
+            *rp = Op<OP_SUM, T>::apply(base, v);
+          } else if constexpr (ATOM) {
+            base = fetch_add_g(rp, v);
+          } else {
+            const int which = wc_off(cd[j0].onf) == 0 ? 0 : 1;
+            rtot[(int64_t)(2 * blockIdx.x + which) * bs + c] = v;
+          }
+        }
+        const uint64_t tge = tm & ~((1ull << lane) - 1);  // tails at or above this lane
+        const int tl = tge ? __ffsll((unsigned long long)tge) - 1 : 64;
+        const T b = shfl_idx(base, tl & 63);
+        if (in) cv[j * bs + c] = tl < 64 ? Op<OP_SUM, T>::apply(b, ex) : ex;
+        if (g > 0 && !(hm & 1) && tm) {  // a run from earlier groups ends here
+          const T b0 = shfl_idx(base, __ffsll((unsigned long long)tm) - 1);
+          for (int jj = jh + lane; jj < g; jj += 64) cv[jj * bs + c] = Op<OP_SUM, T>::apply(b0, cv[jj * bs + c]);
+        }
+        carry = shfl_idx(v, 63);
+        const int s63 = __shfl(s0, 63);
+        jh = s63 < 0 ? jh : g + s63;
       }
-      T *rp = root + (int64_t)r * bs + c;
-      T base;
-      if (wc_first(cd[j].onf) && wc_last(cd[j1 - 1].onf)) {
-        base = *rp;
-        *rp = Op<OP_SUM, T>::apply(base, run);
-      } else if constexpr (ATOM) {
-        base = fetch_add_g(rp, run);
-      } else {
-        const int which = wc_off(cd[j].onf) == 0 ? 0 : 1;
-        rtot[(int64_t)(2 * blockIdx.x + which) * bs + c] = run;
-        base = T(0);
-      }
-      for (int jj = j; jj < j1; jj++) cv[jj * bs + c] = Op<OP_SUM, T>::apply(base, cv[jj * bs + c]);
     }
     __syncthreads();
     // 3: exclusive prefix inside each chunk plus the chunk's base
