@@ -407,6 +407,57 @@ __device__ __forceinline__ void win_load_key(V *lds, const T *__restrict__ scr, 
   }
 }
 
+// Ops whose result does not depend on the order in which the elements are
+// combined: a maximum or minimum under a total order (MAXLOC breaks ties by
+// the smaller index, so it is one too) and wrapping integer addition.  Their
+// chunk reductions read the elements interleaved across the lanes (no LDS
+// bank conflicts) and combine lanes with DPP row moves instead of LDS
+// permutes; floating-point sums keep the canonical pairwise tree.
+template <typename V, int OP>
+struct OrderFree {
+  static constexpr bool value =
+      OP == OP_MAX || OP == OP_MIN || OP == OP_MAXLOC || (OP == OP_SUM && std::is_integral<V>::value);
+  static constexpr bool idempotent = OP != OP_SUM;
+};
+
+// v from the lane that the DPP control CTRL selects, for every 32-bit word
+// of V (a pair's padding word is not moved).
+template <int CTRL, typename V>
+__device__ __forceinline__ V dpp_mov(V v) {
+  constexpr int N = std::is_same<V, Pair>::value ? 3 : (int)(sizeof(V) / 4);
+  static_assert(sizeof(V) % 4 == 0, "32-bit words");
+  int w[sizeof(V) / 4];
+  __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+  for (int k = 0; k < N; k++) w[k] = __builtin_amdgcn_mov_dpp(w[k], CTRL, 0xf, 0xf, false);
+  V r;
+  __builtin_memcpy(&r, w, sizeof(V));
+  return r;
+}
+template <typename V>
+__device__ __forceinline__ V read_lane(V v, int l) {
+  int w[sizeof(V) / 4];
+  __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(V) / 4); k++) w[k] = __builtin_amdgcn_readlane(w[k], l);
+  V r;
+  __builtin_memcpy(&r, w, sizeof(V));
+  return r;
+}
+// Reduction of one value per lane over the whole wavefront (all lanes
+// active), for an order-free op: every lane of a 16-lane row first holds the
+// row's reduction (quad swaps, then the half-row and row mirrors), then the
+// four rows are combined.
+template <int OP, typename V>
+__device__ __forceinline__ V wave_reduce_free(V v) {
+  v = Op<OP, V>::apply(v, dpp_mov<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = Op<OP, V>::apply(v, dpp_mov<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = Op<OP, V>::apply(v, dpp_mov<0x141>(v));  // row_half_mirror
+  v = Op<OP, V>::apply(v, dpp_mov<0x140>(v));  // row_mirror
+  return Op<OP, V>::apply(Op<OP, V>::apply(read_lane(v, 0), read_lane(v, 16)),
+                          Op<OP, V>::apply(read_lane(v, 32), read_lane(v, 48)));
+}
+
 template <typename T, int OP, bool ATOM>
 __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot,
                                                const DevWChunk *__restrict__ wchunk,
@@ -451,6 +502,21 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
   for (int j = wv; j < nb; j += kStageThreads / 64) {
     const int32_t onf = cd[j].onf;
     const int n = wc_n(onf);
+    if constexpr (OrderFree<V, OP>::value) {
+      const int o0 = wc_off(onf);
+      for (int c = 0; c < bs; c++) {
+        // lanes past the chunk's end take its first element (a repeat that
+        // an idempotent op ignores) or the sum's zero
+        V a = lane < n ? ld(lds + (o0 + lane) * bs + c)
+                       : (OrderFree<V, OP>::idempotent ? ld(lds + o0 * bs + c) : V{});
+#pragma unroll
+        for (int s = 1; s < LPT; s++)
+          if (s * 64 + lane < n) a = Op<OP, V>::apply(a, ld(lds + (o0 + s * 64 + lane) * bs + c));
+        const V v = wave_reduce_free<OP>(a);
+        if (lane == 0) st(cv + j * bs + c, (T)lds_value<K>(v));
+      }
+      continue;
+    }
     const int o = wc_off(onf) + lane * LPT;
     const int m = n - lane * LPT;
     for (int c = 0; c < bs; c++) {
@@ -473,20 +539,46 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
-    const int j = q / bs, c = q - j * bs;
-    if constexpr (ATOM) {
-      const int32_t r = cd[j].root;
-      if (j > 0 && cd[j - 1].root == r) continue;  // not the first chunk of its run
-      T acc = ld(cv + q);
-      int j1 = j + 1;
-      for (; j1 < nb && cd[j1].root == r; j1++) acc = Op<OP, T>::apply(acc, ld(cv + j1 * bs + c));
-      T *rp = root + (int64_t)r * bs + c;
-      if (wc_first(cd[j].onf) && wc_last(cd[j1 - 1].onf))
-        st(rp, Op<OP, T>::apply(ld(rp), acc));
-      else
-        AtomicG<OP, T>::run(rp, acc);
-    } else {
+  if constexpr (ATOM) {
+    // per run (the chunks of one root in this window): the combination of
+    // its chunk results by a segmented scan, one wavefront per unit
+    // component, 64 chunks at a time; the run's last lane updates the root,
+    // plainly when the window holds the whole root, else atomically
+    for (int c = wv; c < bs; c += kStageThreads / 64) {
+      T carry{};   // running result of a run continuing from the previous group
+      int jh = 0;  // head chunk of that run
+      for (int g = 0; g < nb; g += 64) {
+        const int j = g + lane;
+        const bool in = j < nb;
+        const int32_t r = in ? cd[j].root : -1;
+        const bool head = in && (j == 0 || cd[j - 1].root != r);
+        const bool tail = in && (j == nb - 1 || cd[j + 1].root != r);
+        T v = in ? ld(cv + j * bs + c) : T{};
+        const uint64_t hm = __ballot(head);
+        const uint64_t hle = hm & (lane == 63 ? ~0ull : (2ull << lane) - 1);
+        const int s0 = hle ? 63 - __clzll(hle) : -1;  // this lane's run head lane, -1: earlier group
+#pragma unroll
+        for (int d = 1; d < 64; d *= 2) {
+          const T y = shfl_up(v, d);
+          if (lane - d >= (s0 < 0 ? 0 : s0)) v = Op<OP, T>::apply(y, v);
+        }
+        if (s0 < 0) v = Op<OP, T>::apply(carry, v);
+        if (tail) {
+          const int j0 = s0 < 0 ? jh : g + s0;
+          T *rp = root + (int64_t)r * bs + c;
+          if (wc_first(cd[j0].onf) && wc_last(cd[j].onf))
+            st(rp, Op<OP, T>::apply(ld(rp), v));
+          else
+            AtomicG<OP, T>::run(rp, v);
+        }
+        carry = shfl_idx(v, 63);
+        const int s63 = __shfl(s0, 63);
+        jh = s63 < 0 ? jh : g + s63;
+      }
+    }
+  } else {
+    for (int q = threadIdx.x; q < nb * bs; q += kStageThreads) {
+      const int j = q / bs, c = q - j * bs;
       const int32_t dst = cd[j].dst;
       if (dst < 0) {
         T *rp = root + (int64_t)(-dst - 1) * bs + c;

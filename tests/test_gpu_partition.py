@@ -116,23 +116,52 @@ def test_partition_holes_and_permuted_slots():
     check(u, wu, "holes fetch leafupdate (holes untouched)")
 
 
+@pytest.mark.parametrize("dtype,bs", [(np.float32, 2), (np.float32, 3), (np.int32, 4), (np.float64, 2),
+                                      (np.int64, 2)])
+@pytest.mark.parametrize("op", ["sum", "max", "min"])
+@pytest.mark.parametrize("mode", ["deterministic", "atomic"])
+def test_partition_units(dtype, bs, op, mode):
+    """Units of several elements (8, 12 and 16 bytes: both unit-size classes
+    of the partitioned path), element-aligned as well as unit-aligned."""
+    from helpers import atomic_sum_tolerance
+    g = inputs.spmv_ghost(seed=12, nroots=4001, nleaves=90007)
+    rng = np.random.default_rng(804 + bs)
+    integer = np.dtype(dtype).kind == "i"
+    leaf = inputs.unit_data(rng, g.leafspace, bs, dtype, "full" if integer else "normal")
+    root = inputs.unit_data(rng, g.nroots, bs, dtype, "full" if integer else "normal")
+    want = oracle.reduce(g.nroots, g.iroot, None, leaf, root, op)
+    off = np.dtype(dtype).itemsize        # element-aligned, not unit-aligned
+    for o in (0, off):
+        sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup(reduce_mode=mode, partition="on")
+        from helpers import unit
+        l, r = dev(leaf, o), dev(root)
+        sf.reduce(l, r, op, unit=unit(root))
+        torch.cuda.synchronize()
+        got = host(r, root)
+        what = f"units {np.dtype(dtype)} x {bs} {op} {mode} offset {o}"
+        if mode == "atomic" and op == "sum" and not integer:
+            ok, worst = atomic_sum_tolerance(got, want, root, leaf, g.iroot, 1e-12 if dtype == np.float64 else 1e-5)
+            assert ok, (what, worst)
+        else:
+            check(got, want, what)
+
+
 @pytest.mark.parametrize("dtype,bs", [(np.float32, 16), (np.int32, 5), (np.float64, 3)])
-def test_partition_units(dtype, bs):
+def test_partition_oversize_units_fall_back(dtype, bs):
+    """Units above 16 bytes take the direct path even with partitioning on."""
     g = inputs.spmv_ghost(seed=12, nroots=4001, nleaves=90007)
     rng = np.random.default_rng(804 + bs)
     leaf = inputs.unit_data(rng, g.leafspace, bs, dtype)
     root = inputs.unit_data(rng, g.nroots, bs, dtype)
     want = oracle.reduce(g.nroots, g.iroot, None, leaf, root)
     check(run_reduce(g, leaf, root, "sum", "on"), want, f"units {bs}")
-    off = np.dtype(dtype).itemsize        # element-aligned, not unit-aligned
-    check(run_reduce(g, leaf, root, "sum", "on", offset=off), want, f"units {bs} offset {off}")
 
 
 def test_partition_halo_and_single_root():
     g = inputs.halo3d(13)
     rng = np.random.default_rng(805)
-    leaf = rng.standard_normal((g.leafspace, 3))
-    root = rng.standard_normal((g.nroots, 3))
+    leaf = rng.standard_normal((g.leafspace, 2))
+    root = rng.standard_normal((g.nroots, 2))
     check(run_reduce(g, leaf, root, "sum", "on"), oracle.reduce(g.nroots, g.iroot, None, leaf, root), "halo")
     n = 200003
     g1 = inputs.Graph(2, np.full(n, 1, np.int64), None, np.zeros(n, np.int64), n)
@@ -233,17 +262,17 @@ def test_partition_atomic_holes_and_units():
     from helpers import atomic_sum_tolerance, check_fetch_chain
     g = inputs.single_sf(seed=14, nroots=5000, nleaves=70001, leafspace=90001)
     rng = np.random.default_rng(813)
-    leaf = rng.standard_normal((g.leafspace, 3))
-    root = rng.standard_normal((g.nroots, 3))
+    leaf = rng.standard_normal((g.leafspace, 2))
+    root = rng.standard_normal((g.nroots, 2))
     want = oracle.reduce(g.nroots, g.iroot, g.ilocal, leaf, root)
     got = run_reduce_mode(g, leaf, root, "sum", "atomic")
     slots = g.ilocal
     ok, worst = atomic_sum_tolerance(got, want, root, leaf[slots], g.iroot, 1e-12)
     assert ok, worst
-    li = inputs.unit_data(rng, g.leafspace, 5, np.int32, "full")
-    ri = inputs.unit_data(rng, g.nroots, 5, np.int32, "full")
+    li = inputs.unit_data(rng, g.leafspace, 3, np.int32, "full")
+    ri = inputs.unit_data(rng, g.nroots, 3, np.int32, "full")
     check(run_reduce_mode(g, li, ri, "max", "atomic"), oracle.reduce(g.nroots, g.iroot, g.ilocal, li, ri, "max"),
-          "atomic max bs 5 with holes")
+          "atomic max bs 3 with holes")
     r0 = rng.integers(0, 100, g.nroots).astype(np.int64)
     lf = rng.integers(0, 100, g.leafspace).astype(np.int64)
     u0 = np.full(g.leafspace, -5, np.int64)
