@@ -712,6 +712,20 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop(const DevSWin *__restr
     for (int j = wv; j < nb; j += kStageThreads / 64) {
       const int32_t onf = cd[j].onf;
       const int n = wc_n(onf);
+      if constexpr (ATOM || std::is_integral<T>::value) {
+        // integer sums are exact in any order, and atomic mode fixes no
+        // order: interleaved reads and a DPP reduction
+        const int o0 = wc_off(onf);
+        for (int c = 0; c < bs; c++) {
+          T a = lane < n ? lds[(o0 + lane) * bs + c] : T(0);
+#pragma unroll
+          for (int s = 1; s < LPT; s++)
+            if (s * 64 + lane < n) a = Op<OP_SUM, T>::apply(a, lds[(o0 + s * 64 + lane) * bs + c]);
+          a = wave_reduce_free<OP_SUM>(a);
+          if (lane == 0) cv[j * bs + c] = a;
+        }
+        continue;
+      }
       const int o = wc_off(onf) + lane * LPT;
       for (int c = 0; c < bs; c++) {
         T a = T(0);
