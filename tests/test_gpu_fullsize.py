@@ -100,6 +100,34 @@ def test_spmv_ghost_full_maxloc(spmv, mode):
          f"maxloc {mode}")
 
 
+@pytest.fixture(scope="module")
+def deep_root():
+    """One root of ~17.06M leaves among five: 66.6K level-0 chunk results, so
+    three levels above level 0 (261, 2, 1 results); the other roots take
+    about 3.4K leaves each (one level above level 0)."""
+    n = (1 << 24) + 300000
+    rng = np.random.default_rng(1010)
+    iroot = np.where(rng.random(n) < 0.999, 2, rng.integers(0, 5, n)).astype(np.int64)
+    return inputs.Graph(5, iroot, None, np.zeros(n, np.int64), n)
+
+
+@pytest.mark.parametrize("part", ["on", "off"])
+def test_deep_root_levels(deep_root, part):
+    """Three chunk levels above level 0 give the oracle's bits, on the
+    partitioned and the direct deterministic paths."""
+    g = deep_root
+    rng = np.random.default_rng(1011)
+    sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="deterministic", partition=part)
+    leaf = rng.standard_normal(g.nleaves)
+    root = rng.standard_normal(g.nroots)
+    same(run(sf, "reduce", leaf, root, "sum"), oracle.reduce(g.nroots, g.iroot, None, leaf, root, "sum"),
+         f"deep root sum ({part})")
+    lp = inputs.maxloc_leaves(rng, g.nleaves, ties=True)
+    rp = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    same(run(sf, "reduce", lp, rp, "maxloc"), oracle.reduce(g.nroots, g.iroot, None, lp, rp, "maxloc"),
+         f"deep root maxloc ({part})")
+
+
 def test_spmv_ghost_full_fetch_and_op(spmv):
     g = spmv
     deg = np.bincount(g.iroot, minlength=g.nroots).astype(np.int64)
