@@ -458,6 +458,23 @@ __device__ __forceinline__ V wave_reduce_free(V v) {
                           Op<OP, V>::apply(read_lane(v, 32), read_lane(v, 48)));
 }
 
+// A whole root of an order-free op: its n elements four at a time (loads in
+// flight, one accumulator); positions past n repeat the first element (an
+// idempotent op ignores it) or add the sum's zero.
+template <typename V, int OP>
+__device__ __forceinline__ V small_free(const V *lds, int o, int n, int bs, int c) {
+  const V e0 = ld(lds + o * bs + c);
+  const V pad = OrderFree<V, OP>::idempotent ? e0 : V{};
+  V a = e0;
+  for (int e = 1; e < n; e += 4) {
+    V x[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) x[k] = e + k < n ? ld(lds + (o + e + k) * bs + c) : pad;
+    a = Op<OP, V>::apply(a, Op<OP, V>::apply(Op<OP, V>::apply(x[0], x[1]), Op<OP, V>::apply(x[2], x[3])));
+  }
+  return a;
+}
+
 template <typename T, int OP, bool ATOM>
 __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot,
                                                const DevWChunk *__restrict__ wchunk,
@@ -488,7 +505,8 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
       const int q = q0 + u * kStageThreads;
       if (q >= nsmall) continue;
       const int c = q % bs;
-      const V v = small_tree<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
+      const V v = OrderFree<V, OP>::value ? small_free<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c)
+                                           : small_tree<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
       st(root + (int64_t)sd[u].root * bs + c, Op<OP, T>::apply(rv[u], lds_value<K>(v)));
       __builtin_amdgcn_sched_barrier(0);  // one tree's registers at a time
     }
@@ -590,9 +608,10 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
   }
 }
 
-// Windows of units up to 8 bytes take 64 KB of LDS, so two blocks share a CU
-// when the kernel stays within 64 VGPRs (8 waves per SIMD); wider units
-// leave room for one block per CU.
+// A window of up to 80 KB of LDS (with its chunk tables) lets two blocks
+// share a CU when the kernel stays within 64 VGPRs (8 waves per SIMD); a
+// larger one (a capacity raised for tuning) runs one block per CU.
+constexpr size_t kPassBLdsTwo = 80 * 1024;
 #define SP_REDUCE_ARGS                                                                                             \
   const DevSWin *__restrict__ wins, const DevSRoot *__restrict__ sroot, const DevWChunk *__restrict__ wchunk,     \
       const uint16_t *__restrict__ lpos, const T *__restrict__ scr, T *__restrict__ lvl_out, T *__restrict__ root, \
@@ -937,17 +956,15 @@ size_t part_scratch_need(const sf_s *sf, size_t ub) {
 }
 
 template <typename T, int OP, bool ATOM>
-static int sp_reduce_launch(unsigned gw, const PassBLds &pl, int cls, hipStream_t st, const DevSWin *win,
+static int sp_reduce_launch(unsigned gw, const PassBLds &pl, hipStream_t st, const DevSWin *win,
                             const DevSRoot *sroot, const DevWChunk *wchunk, const uint16_t *lpos, const T *scr,
                             T *lvl_out, T *root, int bs) {
-  if constexpr (sizeof(T) <= 8) {
-    if (cls == 0) {
-      int rc = allow_lds((const void *)&k_sp_reduce2<T, OP, ATOM>, pl.bytes);
-      if (rc) return rc;
-      hipLaunchKernelGGL((k_sp_reduce2<T, OP, ATOM>), dim3(gw), dim3(kStageThreads), pl.bytes, st, win, sroot, wchunk,
-                         lpos, scr, lvl_out, root, bs, pl.cd_off, pl.cv_off);
-      return SF_OK;
-    }
+  if (pl.bytes <= kPassBLdsTwo) {
+    int rc = allow_lds((const void *)&k_sp_reduce2<T, OP, ATOM>, pl.bytes);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_sp_reduce2<T, OP, ATOM>), dim3(gw), dim3(kStageThreads), pl.bytes, st, win, sroot, wchunk,
+                       lpos, scr, lvl_out, root, bs, pl.cd_off, pl.cv_off);
+    return SF_OK;
   }
   int rc = allow_lds((const void *)&k_sp_reduce<T, OP, ATOM>, pl.bytes);
   if (rc) return rc;
@@ -977,13 +994,13 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   const unsigned gw = (unsigned)hs.win.size();
   if constexpr (OP != OP_MAXLOC) {
     if (atomic) {
-      rc = sp_reduce_launch<T, OP, true>(gw, pl, cls, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr,
+      rc = sp_reduce_launch<T, OP, true>(gw, pl, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr,
                                          buf[0], root, bs);
       if (rc) return rc;
       return sp_check();
     }
   }
-  rc = sp_reduce_launch<T, OP, false>(gw, pl, cls, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr, buf[0],
+  rc = sp_reduce_launch<T, OP, false>(gw, pl, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr, buf[0],
                                       root, bs);
   if (rc) return rc;
   for (size_t k = 1; k < h.levels.size(); k++) {

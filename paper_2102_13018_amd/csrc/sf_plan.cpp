@@ -312,13 +312,14 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
 
 // Window and tile sizes per unit-size class (overridable for tuning sweeps).
 static void stage_sizes(int cls, int32_t *ta, int32_t *cap) {
-  // 8192 units both ways: two 64 KB pass-A tiles (units <= 8 B) share a CU,
-  // and one 8192-unit window fills a pass-B block (measured best on
-  // spmv_ghost; 4096 and 16384 are slower).  Tiles take at most 8192
-  // positions (13-bit offsets in pa_loc).
+  // Pass-A tiles of 8192 units (two 64 KB tiles of units <= 8 B share a CU;
+  // at most 8192 positions: 13-bit offsets in pa_loc).  Windows of 64 KB, so
+  // that two pass-B blocks share a CU: 8192 units <= 8 B (4096 and 16384
+  // measured slower on spmv_ghost), 4096 units of 9..16 B (MAXLOC 222 -> 207
+  // us against one 128 KB window per CU).
   const int64_t ub = cls == 0 ? 8 : 16;
   *ta = 8192;
-  *cap = 8192;
+  *cap = cls == 0 ? 8192 : 4096;
   if (const char *e = getenv(cls == 0 ? "SF_SP0_CAP" : "SF_SP1_CAP")) *cap = atoi(e);
   if (const char *e = getenv(cls == 0 ? "SF_SP0_TA" : "SF_SP1_TA")) *ta = atoi(e);
   *cap = std::max<int32_t>(kChunk, std::min<int32_t>(*cap, (int32_t)(kStageMaxLds / ub)));
