@@ -458,6 +458,39 @@ __device__ __forceinline__ V wave_reduce_free(V v) {
                           Op<OP, V>::apply(read_lane(v, 32), read_lane(v, 48)));
 }
 
+// v from the lane that the DPP control CTRL selects, in the rows ROWMASK
+// enables; a lane without a source lane, or in a disabled row, gets old.
+template <int CTRL, int ROWMASK, typename V>
+__device__ __forceinline__ V dpp_upd(V old, V v) {
+  static_assert(sizeof(V) % 4 == 0, "32-bit words");
+  int wo[sizeof(V) / 4], wv[sizeof(V) / 4];
+  __builtin_memcpy(wo, &old, sizeof(V));
+  __builtin_memcpy(wv, &v, sizeof(V));
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(V) / 4); k++) wo[k] = __builtin_amdgcn_update_dpp(wo[k], wv[k], CTRL, ROWMASK, 0xf, false);
+  V r;
+  __builtin_memcpy(&r, wo, sizeof(V));
+  return r;
+}
+// Inclusive sum over the wavefront (all lanes active), and the exclusive one
+// beside it: shifts by 1, 2, 4, 8 inside each 16-lane row, then the end of
+// row 0 (2) added to row 1 (3), then lane 31 added to rows 2 and 3; the
+// exclusive value is the inclusive one shifted by a lane.  The sums are
+// associated differently from a lane-order fold: exact for integers, any
+// order is allowed where this is used on floating point (atomic mode).
+template <typename T>
+__device__ __forceinline__ T wave_scan_sum(T v, T &excl) {
+  const T z = T(0);
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x111, 0xf>(z, v));  // row_shr:1
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x112, 0xf>(z, v));  // row_shr:2
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x114, 0xf>(z, v));  // row_shr:4
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x118, 0xf>(z, v));  // row_shr:8
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x142, 0xa>(z, v));  // row_bcast:15 into rows 1, 3
+  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x143, 0xc>(z, v));  // row_bcast:31 into rows 2, 3
+  excl = dpp_upd<0x138, 0xf>(z, v);                        // wave_shr:1
+  return v;
+}
+
 // A whole root of an order-free op: its n elements four at a time (loads in
 // flight, one accumulator); positions past n repeat the first element (an
 // idempotent op ignores it) or add the sum's zero.
@@ -674,14 +707,8 @@ __device__ __forceinline__ void chunk_apply(T *lds, const DevWChunk *cd, const T
         x[s] = s < m ? lds[(o + s) * bs + c] : T(0);
         lane_sum = Op<OP_SUM, T>::apply(lane_sum, x[s]);
       }
-      T inc = lane_sum;
-#pragma unroll
-      for (int d = 1; d < 64; d *= 2) {
-        const T o2 = shfl_up(inc, d);
-        if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o2);
-      }
-      T excl = shfl_up(inc, 1);
-      if (lane == 0) excl = T(0);
+      T excl;
+      wave_scan_sum(lane_sum, excl);
       T a = Op<OP_SUM, T>::apply(base[j * bs + c], excl);
 #pragma unroll
       for (int s = 0; s < LPT; s++) {
