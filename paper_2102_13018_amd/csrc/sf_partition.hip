@@ -491,6 +491,28 @@ __device__ __forceinline__ T wave_scan_sum(T v, T &excl) {
   return v;
 }
 
+// Lane steps of the canonical chunk tree (lane l holds the tree of its LPT
+// leaves; lanes combine at distances 1, 2, ..., 32 while the partner's block
+// starts below n), with the same operands in the same order as a shuffle
+// tree: DPP moves inside 16-lane rows (quad swaps, row shifts by 4 and 8),
+// then the four row results read from lanes 0, 16, 32, 48.
+template <int OP, typename V>
+__device__ __forceinline__ V wave_tree(V v, int lane, int n) {
+  constexpr int LPT = kChunkLPT;
+  V o = dpp_upd<0xB1, 0xf>(v, v);  // quad_perm [1,0,3,2]
+  if ((lane & 1) == 0 && (lane + 1) * LPT < n) v = Op<OP, V>::apply(v, o);
+  o = dpp_upd<0x4E, 0xf>(v, v);  // quad_perm [2,3,0,1]
+  if ((lane & 3) == 0 && (lane + 2) * LPT < n) v = Op<OP, V>::apply(v, o);
+  o = dpp_upd<0x104, 0xf>(v, v);  // row_shl:4
+  if ((lane & 7) == 0 && (lane + 4) * LPT < n) v = Op<OP, V>::apply(v, o);
+  o = dpp_upd<0x108, 0xf>(v, v);  // row_shl:8
+  if ((lane & 15) == 0 && (lane + 8) * LPT < n) v = Op<OP, V>::apply(v, o);
+  const V r0 = read_lane(v, 0), r16 = read_lane(v, 16), r32 = read_lane(v, 32), r48 = read_lane(v, 48);
+  const V a = 16 * LPT < n ? Op<OP, V>::apply(r0, r16) : r0;
+  const V b = 48 * LPT < n ? Op<OP, V>::apply(r32, r48) : r32;
+  return 32 * LPT < n ? Op<OP, V>::apply(a, b) : a;
+}
+
 // A whole root of an order-free op: its n elements four at a time (loads in
 // flight, one accumulator); positions past n repeat the first element (an
 // idempotent op ignores it) or add the sum's zero.
@@ -516,6 +538,9 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
                                                int cv_off) {
   using K = LdsKey<T, OP>;
   using V = typename K::V;  // what the LDS holds: the values, or their keys
+  // order-free evaluation: order-free ops, and any op in atomic mode (which
+  // fixes no order)
+  constexpr bool kFree = OrderFree<V, OP>::value || ATOM;
   extern __shared__ __align__(16) unsigned char smem[];
   V *lds = reinterpret_cast<V *>(smem);
   DevWChunk *cd = reinterpret_cast<DevWChunk *>(smem + cd_off);
@@ -538,8 +563,8 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
       const int q = q0 + u * kStageThreads;
       if (q >= nsmall) continue;
       const int c = q % bs;
-      const V v = OrderFree<V, OP>::value ? small_free<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c)
-                                           : small_tree<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
+      const V v = kFree ? small_free<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c)
+                        : small_tree<V, OP>(lds, sr_off(sd[u].on), sr_n(sd[u].on), bs, c);
       st(root + (int64_t)sd[u].root * bs + c, Op<OP, T>::apply(rv[u], lds_value<K>(v)));
       __builtin_amdgcn_sched_barrier(0);  // one tree's registers at a time
     }
@@ -553,7 +578,7 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
   for (int j = wv; j < nb; j += kStageThreads / 64) {
     const int32_t onf = cd[j].onf;
     const int n = wc_n(onf);
-    if constexpr (OrderFree<V, OP>::value) {
+    if constexpr (kFree) {
       const int o0 = wc_off(onf);
       for (int c = 0; c < bs; c++) {
         // lanes past the chunk's end take its first element (a repeat that
@@ -580,12 +605,7 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
 #pragma unroll
         for (int p = 0; p + d < LPT; p += 2 * d)
           if (p + d < m) x[p] = Op<OP, V>::apply(x[p], x[p + d]);
-      V v = x[0];
-#pragma unroll
-      for (int d = 1; d < 64; d *= 2) {
-        const V o2 = shfl_down(v, d);
-        if ((lane & (2 * d - 1)) == 0 && (lane + d) * LPT < n) v = Op<OP, V>::apply(v, o2);
-      }
+      const V v = wave_tree<OP>(x[0], lane, n);
       if (lane == 0) st(cv + j * bs + c, (T)lds_value<K>(v));
     }
   }
