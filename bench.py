@@ -33,22 +33,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def source_hash():
-    """Hash of the library sources: HBM counters taken on other sources are stale."""
-    import glob
+def library_hash():
+    """Hash of the built library (libsf.so): HBM counters taken on another
+    build of the kernels are stale.  Builds are reproducible, so an edit that
+    leaves the device code alone (a comment) keeps the hash."""
     import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2102_13018_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    path = os.path.join(ROOT, "paper_2102_13018_amd", "libsf.so")
+    try:
+        with open(path, "rb") as fh:
+            return hashlib.sha256(fh.read()).hexdigest()[:16]
+    except OSError:
+        return None
 
 
 def measured_traffic(op):
     """HBM bytes per launch of `op` (all of its kernel dispatches) from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
-    plain copy), or None when the summary is missing or was taken on
-    different kernel sources."""
+    plain copy), or None when the summary is missing or was taken on a
+    different build of the library."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
@@ -56,7 +58,8 @@ def measured_traffic(op):
     except OSError:
         return None
     ops = d.get("ops", {})
-    if d.get("_source_hash") != source_hash() or op not in ops:
+    h = library_hash()
+    if h is None or d.get("_library_hash") != h or op not in ops:
         return None
     return int(ops[op]["fetch_bytes"] + ops[op]["write_bytes"])
 

@@ -1,5 +1,5 @@
-// sf_partition.hip -- the partitioned deterministic path of SFReduce and
-// SFFetchAndOp for large star forests.
+// sf_partition.hip -- the partitioned path of SFReduce and SFFetchAndOp for
+// large star forests, in both reduce modes.
 //
 // The root-sorted order that the deterministic reduction needs visits the
 // leaves at random; on a large leaf array every leaf read is then a request
@@ -13,10 +13,12 @@
 //           chunks of large roots -- from its contiguous scratch range into
 //           LDS, putting every leaf at its root-sorted place, and evaluates
 //           the canonical pairwise trees from there.
-// The trees are the same as those of the direct kernels, so results are
-// bit-identical to them (and to the oracle).  FetchAndOp writes the fetched
-// values back into the window (pass B) and moves them to leafupdate with
-// the reverse of pass A (pass C).
+// Deterministic floating-point sums take the same trees as the direct
+// kernels, so results are bit-identical to them (and to the oracle); ops
+// whose result does not depend on the order (MAX, MIN, MAXLOC, integer
+// sums), and every op in atomic mode, combine in whatever order is fastest.
+// FetchAndOp writes the fetched values back into the window (pass B) and
+// moves them to leafupdate with the reverse of pass A (pass C).
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
