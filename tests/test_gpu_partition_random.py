@@ -1,0 +1,123 @@
+"""GPU parity of the partitioned path on seeded random star forests.
+
+Each case draws a graph -- Zipf-skewed roots (exponent 0.6 to 1.6), a few
+giant roots over a uniform background, or uniform roots with holes in the
+leaf space -- of up to 50,000 roots and 400,000 leaves, and a unit inside the
+path's 16-byte limit.  Partitioning is forced on.  Every Reduce op runs in
+both modes and FetchAndOp in both modes: bit-exact against the oracle, except
+the atomic floating-point sum (within the stated tolerance) and the atomic
+fetched values (a valid prefix chain)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2102_13018_amd import inputs
+from paper_2102_13018_amd import sf as S
+from helpers import atomic_sum_tolerance, check_fetch_chain, dev, first_diff, host, same_bits, unit
+
+pytestmark = pytest.mark.gpu
+
+UNITS = [(np.float64, 1), (np.float32, 1), (np.int32, 1), (np.int64, 1), (np.float32, 2), (np.float32, 3),
+         (np.int32, 4), (np.float64, 2), (np.int64, 2)]
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def check(got, want, what):
+    if not same_bits(got, want):
+        idx, a, b = first_diff(got, want)
+        raise AssertionError(f"{what}: differs at {idx.tolist()}: got {a} want {b}")
+
+
+def random_graph(case):
+    rng = np.random.default_rng(9000 + case)
+    nroots = int(rng.integers(1, 50_000))
+    nleaves = int(rng.integers(1, 400_000))
+    kind = case % 3
+    if kind == 0:
+        s = float(rng.uniform(0.6, 1.6))
+        return inputs.spmv_ghost(seed=9100 + case, nroots=nroots, nleaves=nleaves, zipf_s=s,
+                                 nseg=int(rng.integers(1, 65)))
+    if kind == 1:
+        giants = int(rng.integers(1, 5))
+        iroot = rng.integers(0, nroots, nleaves).astype(np.int64)
+        hot = rng.random(nleaves) < 0.7
+        iroot[hot] = rng.integers(0, min(giants, nroots), int(hot.sum()))
+        return inputs.Graph(nroots, iroot, None, np.zeros(nleaves, np.int64), nleaves)
+    return inputs.single_sf(seed=9200 + case, nroots=nroots, nleaves=nleaves,
+                            leafspace=nleaves + int(rng.integers(0, nleaves + 1)))
+
+
+def run(g, mode, fn):
+    sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup(reduce_mode=mode, partition="on")
+    out = fn(sf)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_partition_random_graph(case):
+    g = random_graph(case)
+    rng = np.random.default_rng(9300 + case)
+    dtype, bs = UNITS[int(rng.integers(0, len(UNITS)))]
+    integer = np.dtype(dtype).kind == "i"
+    leaf = inputs.unit_data(rng, g.leafspace, bs, dtype, "full" if integer else "normal")
+    root = inputs.unit_data(rng, g.nroots, bs, dtype, "full" if integer else "normal")
+    slots = g.ilocal if g.ilocal is not None else np.arange(g.nleaves)
+    label = f"case {case}: nroots {g.nroots}, nleaves {g.nleaves}, {np.dtype(dtype)} x {bs}"
+    for op in ("sum", "max", "min"):
+        want = oracle.reduce(g.nroots, g.iroot, g.ilocal, leaf, root, op)
+        for mode in ("deterministic", "atomic"):
+            def red(sf):
+                l, r = dev(leaf), dev(root)
+                sf.reduce(l, r, op, unit=unit(root))
+                return r
+            got = host(run(g, mode, red), root)
+            if mode == "atomic" and op == "sum" and not integer:
+                ok, worst = atomic_sum_tolerance(got, want, root, leaf[slots], g.iroot,
+                                                 1e-12 if dtype == np.float64 else 1e-5)
+                assert ok, (label, op, mode, worst)
+            else:
+                check(got, want, f"{label}: {op} {mode}")
+    # MAXLOC pairs with ties
+    lp = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    rp = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    want = oracle.reduce(g.nroots, g.iroot, g.ilocal, lp, rp, "maxloc")
+    for mode in ("deterministic", "atomic"):
+        def red(sf):
+            l, r = dev(lp), dev(rp)
+            sf.reduce(l, r, "maxloc", unit=unit(rp))
+            return r
+        check(host(run(g, mode, red), rp), want, f"{label}: maxloc {mode}")
+    # FetchAndOp SUM on integers of the drawn width (or int64), values in [0, 100)
+    fdt = dtype if integer else np.int64
+    fbs = bs if integer else 1
+    r0 = inputs.unit_data(rng, g.nroots, fbs, fdt, "u100")
+    lf = inputs.unit_data(rng, g.leafspace, fbs, fdt, "u100")
+    u0 = np.full_like(lf, -7)
+    wr, wu = oracle.fetch_and_op(g.nroots, g.iroot, g.ilocal, r0, lf, u0)
+    for mode in ("deterministic", "atomic"):
+        def fop(sf):
+            r, l, u = dev(r0), dev(lf), dev(u0)
+            sf.fetch_and_op(r, l, u, "sum", unit=unit(r0))
+            return r, u
+        r, u = run(g, mode, fop)
+        r, u = host(r, r0), host(u, u0)
+        check(r, wr, f"{label}: fetch roots {mode}")
+        if mode == "deterministic":
+            check(u, wu, f"{label}: fetch leafupdate {mode}")
+        else:
+            holes = np.ones(g.leafspace, bool)
+            holes[slots] = False
+            assert (u[holes] == -7).all(), f"{label}: holes written"
+            if fbs == 1:
+                check_fetch_chain(g.iroot, slots, r0, lf, u, r)
+            else:
+                for c in range(fbs):
+                    check_fetch_chain(g.iroot, slots, r0[:, c], lf[:, c], u[:, c], r[:, c])
