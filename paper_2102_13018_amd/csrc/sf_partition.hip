@@ -412,9 +412,10 @@ __device__ __forceinline__ void win_load_key(V *lds, const T *__restrict__ scr, 
 // Ops whose result does not depend on the order in which the elements are
 // combined: a maximum or minimum under a total order (MAXLOC breaks ties by
 // the smaller index, so it is one too) and wrapping integer addition.  Their
-// chunk reductions read the elements interleaved across the lanes (no LDS
-// bank conflicts) and combine lanes with DPP row moves instead of LDS
-// permutes; floating-point sums keep the canonical pairwise tree.
+// chunk reductions (and those of every op in atomic mode, which fixes no
+// order) read the elements interleaved across the lanes (no LDS bank
+// conflicts) and combine lanes with DPP row moves instead of LDS permutes;
+// deterministic floating-point sums keep the canonical pairwise tree.
 template <typename V, int OP>
 struct OrderFree {
   static constexpr bool value =
@@ -475,9 +476,9 @@ __device__ __forceinline__ V dpp_upd(V old, V v) {
   return r;
 }
 // Inclusive sum over the wavefront (all lanes active), and the exclusive one
-// beside it: shifts by 1, 2, 4, 8 inside each 16-lane row, then the end of
-// row 0 (2) added to row 1 (3), then lane 31 added to rows 2 and 3; the
-// exclusive value is the inclusive one shifted by a lane.  The sums are
+// beside it: shifts by 1, 2, 4, 8 inside each 16-lane row, then the last lane
+// of rows 0 and 2 added to rows 1 and 3, then lane 31 added to rows 2 and 3;
+// the exclusive value is the inclusive one shifted by a lane.  The sums are
 // associated differently from a lane-order fold: exact for integers, any
 // order is allowed where this is used on floating point (atomic mode).
 template <typename T>
@@ -515,9 +516,10 @@ __device__ __forceinline__ V wave_tree(V v, int lane, int n) {
   return 32 * LPT < n ? Op<OP, V>::apply(a, b) : a;
 }
 
-// A whole root of an order-free op: its n elements four at a time (loads in
-// flight, one accumulator); positions past n repeat the first element (an
-// idempotent op ignores it) or add the sum's zero.
+// A whole root of an order-free op (or of any op in atomic mode): its n
+// elements four at a time (loads in flight, one accumulator); positions past
+// n repeat the first element (an idempotent op ignores it) or add the sum's
+// zero.
 template <typename V, int OP>
 __device__ __forceinline__ V small_free(const V *lds, int o, int n, int bs, int c) {
   const V e0 = ld(lds + o * bs + c);
