@@ -33,24 +33,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def library_hash():
-    """Hash of the built library (libsf.so): HBM counters taken on another
-    build of the kernels are stale.  Builds are reproducible, so an edit that
-    leaves the device code alone (a comment) keeps the hash."""
+def device_code_hash():
+    """Hash of the library's device code (the .hip_fatbin section of
+    libsf.so; the whole file if that section is not found): HBM counters
+    taken on other kernels are stale.  Builds are reproducible, so an edit of
+    host code or comments keeps the hash."""
     import hashlib
+    import struct
     path = os.path.join(ROOT, "paper_2102_13018_amd", "libsf.so")
     try:
         with open(path, "rb") as fh:
-            return hashlib.sha256(fh.read()).hexdigest()[:16]
+            b = fh.read()
     except OSError:
         return None
+    data = b
+    if b[:4] == b"\x7fELF" and b[4] == 2:  # 64-bit ELF: find the section
+        shoff, = struct.unpack_from("<Q", b, 0x28)
+        shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+        secs = [struct.unpack_from("<IIQQQQIIQQ", b, shoff + i * shentsize) for i in range(shnum)]
+        names = secs[shstrndx][4]
+        for sec in secs:
+            end = b.index(b"\0", names + sec[0])
+            if b[names + sec[0]:end] == b".hip_fatbin":
+                data = b[sec[4]:sec[4] + sec[5]]
+                break
+    return hashlib.sha256(data).hexdigest()[:16]
 
 
 def measured_traffic(op):
     """HBM bytes per launch of `op` (all of its kernel dispatches) from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
     plain copy), or None when the summary is missing or was taken on a
-    different build of the library."""
+    different device code."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
@@ -58,8 +72,8 @@ def measured_traffic(op):
     except OSError:
         return None
     ops = d.get("ops", {})
-    h = library_hash()
-    if h is None or d.get("_library_hash") != h or op not in ops:
+    h = device_code_hash()
+    if h is None or d.get("_device_code_hash") != h or op not in ops:
         return None
     return int(ops[op]["fetch_bytes"] + ops[op]["write_bytes"])
 

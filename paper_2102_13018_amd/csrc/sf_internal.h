@@ -32,7 +32,12 @@ constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
 // through a window-major scratch copy of the leaves):
 constexpr int kStageThreads = 1024;      // threads per block of the staged kernels
 constexpr int kStageMaxLds = 131072;     // LDS of one staged block (bytes)
-constexpr int64_t kPartitionMin = 1 << 20;  // automatic partitioning from this many leaves
+// Automatic partitioning (SFs with repeated roots): the plans are built from
+// kPartitionFopMin leaves, where the deterministic FetchAndOp already gains
+// from them; Reduce and the atomic FetchAndOp use them from kPartitionMin
+// leaves (measured crossovers on a Zipf SF).
+constexpr int64_t kPartitionMin = 1 << 19;
+constexpr int64_t kPartitionFopMin = 1 << 16;
 
 // --------------------------------------------------------- device structs
 // Pattern of one side of a segment: index(t) = start + i + sy*j + sz*k with
@@ -118,7 +123,8 @@ struct HostPlan {
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
   // partitioned deterministic path: one plan per unit-size class
   // (class 0: units of <= 8 bytes, class 1: units of 9..16 bytes)
-  bool part = false;
+  bool part = false;      // the partition plans are built
+  bool part_all = false;  // ... and serve every op (else only the deterministic FetchAndOp)
   struct Stage {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     int32_t maxbig = 0;               // most level-0 chunks in one window

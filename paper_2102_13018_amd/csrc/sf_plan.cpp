@@ -535,7 +535,7 @@ int analyze(sf_s *sf) {
 
   // ---- partitioned deterministic path
   const int pmode = sf->opts.partition;  // 0 auto, 1 on, 2 off
-  if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionMin))) {
+  if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionFopMin))) {
     std::vector<int32_t> proc_slot(L);
     for (int64_t p = 0; p < L; p++) proc_slot[p] = (int32_t)slot(proc_leaf[p]);
     // the two unit-size classes read the shared plan and write only their
@@ -561,6 +561,7 @@ int analyze(sf_s *sf) {
     for (int rc : rcs)
       if (rc) return rc;
     hp.part = true;
+    hp.part_all = pmode == 1 || L >= kPartitionMin;
   }
 
   sf->segments = std::move(segs);
