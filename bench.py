@@ -91,6 +91,9 @@ def parse():
                    help="run one row alone (for a profiler) and print its JSON")
     p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
     p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
+    p.add_argument("--partition-sweep", action="store_true",
+                   help="time Reduce SUM f64 and FetchAndOp SUM int64 with partitioning off / on / auto on "
+                        "Zipf SFs of 2^16..2^21 leaves (the automatic threshold's evidence)")
     return p.parse_args()
 
 
@@ -419,6 +422,34 @@ def autograd_row(torch, S, inputs, steps):
             "sf_GBps_lower_bound": round(sf_bytes / ms / 1e6, 1)}
 
 
+def partition_sweep(torch, S, inputs, steps):
+    """Median device time (us) of Reduce SUM f64 and FetchAndOp SUM int64 in
+    both modes, with the partitioned path off, on and automatic, on Zipf SFs
+    of 2^16..2^21 leaves (nroots = nleaves / 8)."""
+    out = {}
+    for lg in range(16, 22):
+        L = 1 << lg
+        g = inputs.spmv_ghost(seed=3, nroots=max(1, L // 8), nleaves=L)
+        rng = np.random.default_rng(1)
+        leaf = torch.from_numpy(rng.standard_normal(L)).cuda()
+        root = torch.from_numpy(rng.standard_normal(g.nroots)).cuda()
+        li = torch.ones(L, dtype=torch.int64, device="cuda")
+        ri = torch.zeros(g.nroots, dtype=torch.int64, device="cuda")
+        ui = torch.zeros(L, dtype=torch.int64, device="cuda")
+        row = {}
+        for part in ("off", "on", "auto"):
+            for mode in ("deterministic", "atomic"):
+                sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode=mode, partition=part)
+                ops = [Op("reduce", lambda: sf.reduce(leaf, root, "sum", unit=S.SfUnit(S.SF_F64, 1)), 0, ""),
+                       Op("fetch", lambda: sf.fetch_and_op(ri, li, ui, "sum", unit=S.SfUnit(S.SF_I64, 1)), 0, "")]
+                time_ops(torch, ops, steps, 3)
+                for o in ops:
+                    row[f"{o.name}_{mode[:3]}_{part}"] = round(float(np.median(o.times)) * 1e3, 1)
+        out[f"2^{lg}"] = row
+        log(f"2^{lg}: {row}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -444,6 +475,10 @@ def main():
         del a, b
         if not args.profile_op:
             return
+
+    if args.partition_sweep:
+        print(json.dumps({"partition_sweep": partition_sweep(torch, S, inputs, args.steps)}), flush=True)
+        return
 
     if args.only_row:
         fn = {"halo": halo_row, "batch": batch_row, "autograd": autograd_row}[args.only_row]
