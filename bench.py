@@ -93,7 +93,7 @@ def parse():
     p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
     p.add_argument("--partition-sweep", action="store_true",
                    help="time Reduce SUM f64 and FetchAndOp SUM int64 with partitioning off / on / auto on "
-                        "Zipf SFs of 2^16..2^21 leaves (the automatic threshold's evidence)")
+                        "Zipf and uniform SFs of 2^16..2^22 leaves (the automatic threshold's evidence)")
     return p.parse_args()
 
 
@@ -425,28 +425,35 @@ def autograd_row(torch, S, inputs, steps):
 def partition_sweep(torch, S, inputs, steps):
     """Median device time (us) of Reduce SUM f64 and FetchAndOp SUM int64 in
     both modes, with the partitioned path off, on and automatic, on Zipf SFs
-    of 2^16..2^21 leaves (nroots = nleaves / 8)."""
+    (nroots = nleaves / 8) and on SFs with uniform roots of mean degree 2 and
+    8, of 2^16..2^22 leaves."""
     out = {}
-    for lg in range(16, 22):
-        L = 1 << lg
-        g = inputs.spmv_ghost(seed=3, nroots=max(1, L // 8), nleaves=L)
-        rng = np.random.default_rng(1)
-        leaf = torch.from_numpy(rng.standard_normal(L)).cuda()
-        root = torch.from_numpy(rng.standard_normal(g.nroots)).cuda()
-        li = torch.ones(L, dtype=torch.int64, device="cuda")
-        ri = torch.zeros(g.nroots, dtype=torch.int64, device="cuda")
-        ui = torch.zeros(L, dtype=torch.int64, device="cuda")
-        row = {}
-        for part in ("off", "on", "auto"):
-            for mode in ("deterministic", "atomic"):
-                sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode=mode, partition=part)
-                ops = [Op("reduce", lambda: sf.reduce(leaf, root, "sum", unit=S.SfUnit(S.SF_F64, 1)), 0, ""),
-                       Op("fetch", lambda: sf.fetch_and_op(ri, li, ui, "sum", unit=S.SfUnit(S.SF_I64, 1)), 0, "")]
-                time_ops(torch, ops, steps, 3)
-                for o in ops:
-                    row[f"{o.name}_{mode[:3]}_{part}"] = round(float(np.median(o.times)) * 1e3, 1)
-        out[f"2^{lg}"] = row
-        log(f"2^{lg}: {row}")
+    for fam in ("zipf", "uniform2", "uniform8"):
+        for lg in range(16, 23):
+            L = 1 << lg
+            if fam == "zipf":
+                g = inputs.spmv_ghost(seed=3, nroots=max(1, L // 8), nleaves=L)
+            else:
+                R = max(1, L // int(fam[7:]))
+                iroot = np.random.default_rng(lg).integers(0, R, L).astype(np.int64)
+                g = inputs.Graph(R, iroot, None, np.zeros(L, np.int64), L)
+            rng = np.random.default_rng(1)
+            leaf = torch.from_numpy(rng.standard_normal(L)).cuda()
+            root = torch.from_numpy(rng.standard_normal(g.nroots)).cuda()
+            li = torch.ones(L, dtype=torch.int64, device="cuda")
+            ri = torch.zeros(g.nroots, dtype=torch.int64, device="cuda")
+            ui = torch.zeros(L, dtype=torch.int64, device="cuda")
+            row = {}
+            for part in ("off", "on", "auto"):
+                for mode in ("deterministic", "atomic"):
+                    sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode=mode, partition=part)
+                    ops = [Op("reduce", lambda: sf.reduce(leaf, root, "sum", unit=S.SfUnit(S.SF_F64, 1)), 0, ""),
+                           Op("fetch", lambda: sf.fetch_and_op(ri, li, ui, "sum", unit=S.SfUnit(S.SF_I64, 1)), 0, "")]
+                    time_ops(torch, ops, steps, 3)
+                    for o in ops:
+                        row[f"{o.name}_{mode[:3]}_{part}"] = round(float(np.median(o.times)) * 1e3, 1)
+            out[f"{fam} 2^{lg}"] = row
+            log(f"{fam} 2^{lg}: {row}")
     return out
 
 

@@ -106,11 +106,12 @@ typedef struct {
   int32_t use_patterns; /* 1 (default): detect contiguous / 3-D sub-block index patterns */
   int32_t analyze_only; /* 1: host analysis only, no device memory (for inspection) */
   int32_t partition;    /* Reduce / FetchAndOp through window-major scratch (units of at most
-                           16 bytes, SFs with repeated roots): 0 auto (Reduce and the atomic
-                           FetchAndOp on SFs of 2^19 leaves or more, the deterministic
-                           FetchAndOp from 2^16 leaves), 1 always, 2 never.  Deterministic
-                           results are identical either way; atomic results meet the same bar
-                           either way. */
+                           16 bytes, SFs with repeated roots): 0 auto (the deterministic
+                           FetchAndOp from 2^16 leaves, the atomic Reduce from 2^19, the
+                           deterministic Reduce from 2^19 when some root has more than 32
+                           leaves and from 2^20 otherwise, the atomic FetchAndOp from 2^20),
+                           1 always, 2 never.  Deterministic results are identical either way;
+                           atomic results meet the same bar either way. */
 } sf_setup_opts;
 
 /* Index pattern of one side of one segment (Section 5.2): index(t) for the

@@ -32,12 +32,16 @@ constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
 // through a window-major scratch copy of the leaves):
 constexpr int kStageThreads = 1024;      // threads per block of the staged kernels
 constexpr int kStageMaxLds = 131072;     // LDS of one staged block (bytes)
-// Automatic partitioning (SFs with repeated roots): the plans are built from
-// kPartitionFopMin leaves, where the deterministic FetchAndOp already gains
-// from them; Reduce and the atomic FetchAndOp use them from kPartitionMin
-// leaves (measured crossovers on a Zipf SF).
-constexpr int64_t kPartitionMin = 1 << 19;
-constexpr int64_t kPartitionFopMin = 1 << 16;
+// Automatic partitioning (SFs with repeated roots), from the crossovers
+// measured on Zipf and uniform SFs: the plans are built from kPartitionPlan
+// leaves, where the deterministic FetchAndOp already gains from them; the
+// atomic Reduce uses them from kPartitionMid leaves, the deterministic Reduce
+// from there when some root has chunk levels (degree > kSmallMaxDeg) and
+// from kPartitionBig leaves otherwise, the atomic FetchAndOp from
+// kPartitionBig leaves.
+constexpr int64_t kPartitionPlan = 1 << 16;
+constexpr int64_t kPartitionMid = 1 << 19;
+constexpr int64_t kPartitionBig = 1 << 20;
 
 // --------------------------------------------------------- device structs
 // Pattern of one side of a segment: index(t) = start + i + sy*j + sz*k with
@@ -123,8 +127,8 @@ struct HostPlan {
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
   // partitioned deterministic path: one plan per unit-size class
   // (class 0: units of <= 8 bytes, class 1: units of 9..16 bytes)
-  bool part = false;      // the partition plans are built
-  bool part_all = false;  // ... and serve every op (else only the deterministic FetchAndOp)
+  bool part = false;  // the partition plans are built (the deterministic FetchAndOp uses them)
+  bool part_red_det = false, part_red_atomic = false, part_fop_atomic = false;  // ... these ops too
   struct Stage {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     int32_t maxbig = 0;               // most level-0 chunks in one window

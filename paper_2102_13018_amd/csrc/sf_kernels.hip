@@ -572,7 +572,7 @@ template <typename T, int OP>
 static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (OP != OP_REPLACE && h.part_all && stage_class((int64_t)sizeof(T) * bs) >= 0)
+  if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)sizeof(T) * bs) >= 0)
     return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
@@ -628,7 +628,7 @@ template <typename T, int OP>
 static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (h.part_all && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
+  if (h.part_red_atomic && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
   const int ntiles = (int)h.tiles.size();
   const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kReduceGrid);
   const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
@@ -707,7 +707,7 @@ template <typename T>
 static int fop_atomic_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (h.part_all && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, true, st);
+  if (h.part_fop_atomic && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, true, st);
   const int ntiles = (int)h.tiles.size();
   if (!h.hot_roots.empty()) {
     const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kFetchGrid);

@@ -535,7 +535,7 @@ int analyze(sf_s *sf) {
 
   // ---- partitioned deterministic path
   const int pmode = sf->opts.partition;  // 0 auto, 1 on, 2 off
-  if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionFopMin))) {
+  if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionPlan))) {
     std::vector<int32_t> proc_slot(L);
     for (int64_t p = 0; p < L; p++) proc_slot[p] = (int32_t)slot(proc_leaf[p]);
     // the two unit-size classes read the shared plan and write only their
@@ -561,7 +561,10 @@ int analyze(sf_s *sf) {
     for (int rc : rcs)
       if (rc) return rc;
     hp.part = true;
-    hp.part_all = pmode == 1 || L >= kPartitionMin;
+    const bool levels = maxdeg > kSmallMaxDeg;
+    hp.part_red_atomic = pmode == 1 || L >= kPartitionMid;
+    hp.part_red_det = pmode == 1 || L >= (levels ? kPartitionMid : kPartitionBig);
+    hp.part_fop_atomic = pmode == 1 || L >= kPartitionBig;
   }
 
   sf->segments = std::move(segs);
