@@ -877,7 +877,9 @@ __global__ __launch_bounds__(kStageThreads) void k_sp_fop(const DevSWin *__restr
 // Deterministic FetchAndOp across windows: one wavefront per root that
 // spans windows turns its runs' totals (in window order, i.e. leaf order)
 // into their bases, starting from the root's value, and leaves the root's
-// final value.
+// final value.  Each step takes 64 * kScanPer runs, kScanPer consecutive
+// ones per lane (all their loads in flight), so the longest root -- a few
+// hundred runs -- takes one or two steps.  Integer units only (exact sums).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sp_span_scan(const int32_t *__restrict__ span_first,
                                                          const int32_t *__restrict__ span_slot,
@@ -891,17 +893,32 @@ __global__ __launch_bounds__(kBlock) void k_sp_span_scan(const int32_t *__restri
   T *rp = root + (int64_t)span_root[i] * bs;
   for (int c = 0; c < bs; c++) {
     T carry = rp[c];
-    for (int k0 = a; k0 < b; k0 += 64) {
-      const int k = k0 + lane;
-      const int64_t e = k < b ? (int64_t)span_slot[k] * bs + c : 0;
-      const T v = k < b ? rtot[e] : T(0);
-      T inc = v;
+    for (int k0 = a; k0 < b; k0 += 64 * kScanPer) {
+      int64_t e[kScanPer];
+      T x[kScanPer];
+      T s = T(0);
+#pragma unroll
+      for (int j = 0; j < kScanPer; j++) {
+        const int k = k0 + lane * kScanPer + j;
+        e[j] = k < b ? (int64_t)span_slot[k] * bs + c : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kScanPer; j++) {
+        x[j] = e[j] >= 0 ? rtot[e[j]] : T(0);
+        s = Op<OP_SUM, T>::apply(s, x[j]);
+      }
+      T inc = s;
 #pragma unroll
       for (int d = 1; d < 64; d *= 2) {
         const T o = shfl_up(inc, d);
         if (lane >= d) inc = Op<OP_SUM, T>::apply(inc, o);
       }
-      if (k < b) rbase[e] = Op<OP_SUM, T>::apply(carry, wrap_sub(inc, v));
+      T acc = Op<OP_SUM, T>::apply(carry, wrap_sub(inc, s));
+#pragma unroll
+      for (int j = 0; j < kScanPer; j++) {
+        if (e[j] >= 0) rbase[e[j]] = acc;
+        acc = Op<OP_SUM, T>::apply(acc, x[j]);
+      }
       carry = Op<OP_SUM, T>::apply(carry, shfl_idx(inc, 63));
     }
     if (lane == 0) rp[c] = carry;
