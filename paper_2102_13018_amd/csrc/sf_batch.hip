@@ -295,7 +295,7 @@ static int batch_build_tiles(sf_batch_s *b) {
   });
   const size_t bytes = std::max<size_t>(b->htiles.size(), 1) * sizeof(BatchTile);
   if (bytes > b->dtiles_cap) {
-    if (b->dtiles) hipFree(b->dtiles);
+    if (b->dtiles) (void)hipFree(b->dtiles);  // a new, larger table replaces it
     b->dtiles = nullptr;
     b->dtiles_cap = 0;
     hipError_t e = hipMalloc(&b->dtiles, bytes);
@@ -310,8 +310,8 @@ static int batch_build_tiles(sf_batch_s *b) {
 }
 
 static void batch_free_graph(sf_batch_s *b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -391,7 +391,7 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
     }
     e = hipMemcpy(b->ditems, b->hitems.data(), sizeof(BatchItemDev) * n, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-      hipFree(b->ditems);
+      (void)hipFree(b->ditems);
       delete b;
       return set_hip_error(e);
     }
@@ -457,7 +457,7 @@ extern "C" int sf_batch_graph_capture(sf_batch_t b, int32_t mode, hipStream_t st
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(stream, &graph);
   if (rc) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc;
   }
   if (e != hipSuccess) return set_hip_error(e);
@@ -538,7 +538,7 @@ extern "C" int sf_batch_autotune(sf_batch_t b, const char *cache_path, hipStream
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SF_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return SF_ERR_HIP;
   }
   float best = 1e30f;
@@ -553,12 +553,13 @@ extern "C" int sf_batch_autotune(sf_batch_t b, const char *cache_path, hipStream
       float tot = 0.f;
       const int reps = 5;
       for (int r = 0; r < reps && !rc; r++) {
-        hipEventRecord(e0, stream);
-        rc = sf_batch_launch(b, stream);
-        hipEventRecord(e1, stream);
-        hipEventSynchronize(e1);
+        hipError_t e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) rc = sf_batch_launch(b, stream);
+        if (e == hipSuccess && !rc) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess && !rc) rc = set_hip_error(e);
         tot += ms;
       }
       if (rc) break;
@@ -570,8 +571,8 @@ extern "C" int sf_batch_autotune(sf_batch_t b, const char *cache_path, hipStream
     }
     if (rc) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   rc = sf_batch_set_config(b, best_lpt, best_tile);
   if (rc) return rc;
@@ -589,8 +590,8 @@ extern "C" int sf_batch_destroy(sf_batch_t *pb) {
   sf_batch_s *b = *pb;
   if (!b) return SF_OK;
   batch_free_graph(b);
-  if (b->ditems) hipFree(b->ditems);
-  if (b->dtiles) hipFree(b->dtiles);
+  if (b->ditems) (void)hipFree(b->ditems);
+  if (b->dtiles) (void)hipFree(b->dtiles);
   delete b;
   *pb = nullptr;
   return SF_OK;

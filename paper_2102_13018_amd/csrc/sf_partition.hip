@@ -939,11 +939,12 @@ static int allow_lds(const void *fn, size_t bytes) {
   static std::mutex mu;
   static std::vector<std::pair<std::pair<const void *, int>, size_t>> granted;
   int dev = 0;
-  hipGetDevice(&dev);
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_hip_error(e);
   std::lock_guard<std::mutex> g(mu);
   for (auto &x : granted)
     if (x.first.first == fn && x.first.second == dev && x.second >= bytes) return SF_OK;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return set_hip_error(e);
   granted.push_back({{fn, dev}, bytes});
   return SF_OK;

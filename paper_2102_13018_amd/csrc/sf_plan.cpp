@@ -574,9 +574,9 @@ int analyze(sf_s *sf) {
 }
 
 void free_device(sf_s *sf) {
-  if (sf->dp.blob) hipFree(sf->dp.blob);
-  if (sf->scratch) hipFree(sf->scratch);
-  for (void *p : sf->retired) hipFree(p);
+  if (sf->dp.blob) (void)hipFree(sf->dp.blob);
+  if (sf->scratch) (void)hipFree(sf->scratch);
+  for (void *p : sf->retired) (void)hipFree(p);
   sf->retired.clear();
   sf->dp = DevPlan{};
   sf->scratch = nullptr;
