@@ -210,3 +210,27 @@ def test_index_width_limits():
     assert L.sf_create(1, 1, ok.ctypes.data_as(ctypes.c_void_p), S.SF_COPY_VALUES, p, S.SF_COPY_VALUES,
                        ctypes.byref(h)) == 0
     assert L.sf_destroy(ctypes.byref(h)) == 0
+
+
+def test_bench_traffic_bookkeeping():
+    """The benchmark's HBM counters are keyed on the built library's device
+    code: the hash is stable, read from the .hip_fatbin section, and the
+    committed counters are either for this build or reported as absent."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    h = bench.device_code_hash()
+    assert h is not None and re.fullmatch(r"[0-9a-f]{16}", h)
+    assert bench.device_code_hash() == h
+    assert bench.measured_traffic("no_such_op") is None
+    with open(os.path.join(root, "profiles", "hbm_traffic.json")) as f:
+        d = json.load(f)
+    t = bench.measured_traffic("fetch_and_op_i64_det")
+    if d.get("_device_code_hash") == h:
+        ops = d["ops"]["fetch_and_op_i64_det"]
+        assert t == int(ops["fetch_bytes"] + ops["write_bytes"]) and t > 0
+    else:
+        assert t is None
