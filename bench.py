@@ -85,9 +85,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-rows", action="store_true",
-                   help="time the step only: skip cold-cache times, copy ceiling, direct atomic and halo / batch / "
+                   help="time the step only: skip cold-cache times, copy ceiling, direct atomic and small / halo / batch / "
                         "autograd rows")
-    p.add_argument("--only-row", default=None, choices=["halo", "batch", "autograd"],
+    p.add_argument("--only-row", default=None, choices=["small", "halo", "batch", "autograd"],
                    help="run one row alone (for a profiler) and print its JSON")
     p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
     p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
@@ -305,6 +305,38 @@ def graph_time_us(torch, fn, reps=20):
     return float(np.median(times))
 
 
+def small_row(torch, S, inputs, steps):
+    """The 16K-leaf SF with holes (Fig. 2's kind at test scale): 4096 roots,
+    16384 leaves on a random subset of 20000 slots.  Launch-bound, so each op
+    is timed as 20 graph-captured calls."""
+    g = inputs.single_sf(seed=1)
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(6)
+    deg = np.bincount(g.iroot, minlength=g.nroots)
+    Rt = int((deg > 0).sum())
+    L = g.nleaves
+    idx = 8 * L  # iremote and ilocal (a random subset: no pattern)
+    root = torch.from_numpy(rng.standard_normal(g.nroots)).to(dev)
+    leaf = torch.from_numpy(rng.standard_normal(g.leafspace)).to(dev)
+    ri = torch.from_numpy(rng.integers(0, 100, g.nroots).astype(np.int32)).to(dev)
+    li = torch.from_numpy(rng.integers(0, 100, g.leafspace).astype(np.int32)).to(dev)
+    ui = torch.zeros(g.leafspace, dtype=torch.int32, device=dev)
+    f64, i32 = S.SfUnit(S.SF_F64, 1), S.SfUnit(S.SF_I32, 1)
+    sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup()
+    cases = {
+        "bcast_replace_f64": (lambda: sf.bcast(root, leaf, "replace", unit=f64), L * 8 + Rt * 8 + idx),
+        "reduce_sum_f64": (lambda: sf.reduce(leaf, root, "sum", unit=f64), L * 8 + 2 * Rt * 8 + idx),
+        "reduce_max_f64": (lambda: sf.reduce(leaf, root, "max", unit=f64), L * 8 + 2 * Rt * 8 + idx),
+        "fetch_and_op_i32": (lambda: sf.fetch_and_op(ri, li, ui, "sum", unit=i32), 2 * L * 4 + 2 * Rt * 4 + idx),
+    }
+    out = {}
+    for name, (fn, nb) in cases.items():
+        us = graph_time_us(torch, fn)
+        out[name] = {"us": round(us, 2), "alg_MB": round(nb / 1e6, 3), "GBps": round(nb / us / 1e3, 1)}
+    return {"workload": "single_sf(nroots=4096, nleaves=16384, leafspace=20000)",
+            "timing": "20 calls per HIP graph", "ops": out}
+
+
 def halo_row(torch, S, inputs, steps):
     """Periodic 256^3 halo: pattern path vs generic index path.  The ops are a
     few microseconds long, so each is timed as 20 graph-captured calls."""
@@ -488,7 +520,7 @@ def main():
         return
 
     if args.only_row:
-        fn = {"halo": halo_row, "batch": batch_row, "autograd": autograd_row}[args.only_row]
+        fn = {"small": small_row, "halo": halo_row, "batch": batch_row, "autograd": autograd_row}[args.only_row]
         print(json.dumps({args.only_row: fn(torch, S, inputs, args.steps)}), flush=True)
         return
 
@@ -550,7 +582,8 @@ def main():
                                   "kernel": o.kernels, "traffic": measured_traffic(o.name)}
             log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
         out["row_direct_atomic"] = direct_row
-        for name, fn in (("halo", halo_row), ("batch", batch_row), ("autograd", autograd_row)):
+        for name, fn in (("small", small_row), ("halo", halo_row), ("batch", batch_row),
+                         ("autograd", autograd_row)):
             try:
                 out[f"row_{name}"] = fn(torch, S, inputs, args.steps)
             except Exception as e:  # a row that cannot run is reported, not hidden
