@@ -725,10 +725,11 @@ static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   if (h.part && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_fop_part<T>(sf, root, leaf, upd, bs, false, st);
-  for (int c = 0; c < kNumClasses; c++)
-    if (!h.cls[c].empty())
-      hipLaunchKernelGGL((k_fop_small<T>), dim3(nblocks((int64_t)h.cls[c].size() * bs)), dim3(kBlock), 0, st, d.cls[c],
-                         (int)h.cls[c].size(), d.troot, d.toff, d.sl, root, leaf, upd, bs);
+  // roots of degree <= kSmallMaxDeg: one launch over the degree classes
+  // (concatenated class by class, so a wavefront's threads mostly share one)
+  if (!h.small_all.empty())
+    hipLaunchKernelGGL((k_fop_small<T>), dim3(nblocks((int64_t)h.small_all.size() * bs)), dim3(kBlock), 0, st,
+                       d.small_all, (int)h.small_all.size(), d.troot, d.toff, d.sl, root, leaf, upd, bs);
   const int nch = (int)h.fo_chunks.size();
   const int nlarge = (int)h.large.size();
   if (nch) {
