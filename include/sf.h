@@ -152,7 +152,8 @@ typedef enum {
   SF_ERR_HIP = -5,         /* HIP runtime or launch error */
   SF_ERR_OOM = -6,         /* device or host allocation failed */
   SF_ERR_MISMATCH = -7,    /* *_end without a matching *_begin with the same arguments */
-  SF_ERR_BUSY = -8         /* *_begin while the same operation on the same buffers is pending */
+  SF_ERR_BUSY = -8,        /* *_begin while the same operation on the same buffers is pending */
+  SF_ERR_SCRATCH = -9      /* an allocation-free call needs more scratch than its fixed buffer holds */
 } sf_error;
 
 /* ------------------------------------------------------------- creation */
@@ -204,6 +205,27 @@ int sf_reduce_begin(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata,
                     hipStream_t stream);
 int sf_reduce_end(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
                   hipStream_t stream);
+
+/* sf_reduce_begin for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and end call (sf_reduce_end) as sf_reduce_begin, but no
+ * device or host memory is allocated and nothing is freed: the scratch the
+ * kernels need comes from one fixed device buffer of SF_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per device, which the library holds until the process ends.
+ *  - A large SF whose partitioned path (window-major scratch copy of the
+ *    leaves) needs more than the buffer runs the direct kernels instead:
+ *    identical bits in DETERMINISTIC mode, the same tolerance in ATOMIC mode.
+ *  - SF_ERR_SCRATCH when even the direct kernels need more (chunk levels of
+ *    very large roots with wide units, or MAXLOC in ATOMIC mode with more
+ *    than 8M touched roots x bs); nothing is enqueued then.
+ *  - Every call on a device shares that device's buffer, which keeps the
+ *    last call's contents (no kernel relies on it holding anything at the
+ *    start).  Calls that overlap in time on one device -- on two streams, or
+ *    from two threads -- race on it: order them on one stream.
+ *  - SF_ERR_BUSY also when too many operations of this SF are pending. */
+#define SF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sf_reduce_begin_noalloc(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
+                            hipStream_t stream);
 
 /* SFFetchAndOp (Section 3.2, item 2), op = SUM: every leaf i fetches the
  * current partial value of its root into leafupdate[l_i], then adds

@@ -69,6 +69,12 @@ extern "C" int sf_create(int64_t nroots, int64_t nleaves, const int64_t *ilocal,
   }
   sf->opts.reduce_mode = SF_REDUCE_AUTO;
   sf->opts.use_patterns = 1;
+  try {
+    sf->pending.reserve(kMaxPending);
+  } catch (const std::bad_alloc &) {
+    delete sf;
+    return SF_ERR_OOM;
+  }
   *out = sf;
   return SF_OK;
 }
@@ -191,6 +197,28 @@ extern "C" int sf_reduce_begin(sf_t sf, sf_unit unit, const void *leafdata, void
   return SF_OK;
 }
 
+extern "C" int sf_reduce_begin_noalloc(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
+                                       hipStream_t stream) {
+  if (!sf) return SF_ERR_ARG;
+  std::lock_guard<std::mutex> g(sf->mu);
+  int rc = begin_common(sf, 1, unit, op, rootdata, leafdata, nullptr);
+  if (rc) return rc;
+  // the pending list has room reserved at creation: no host allocation
+  if (sf->pending.size() >= sf->pending.capacity()) return SF_ERR_BUSY;
+  void *p = nullptr;
+  size_t cap = 0;
+  rc = fixed_scratch(&p, &cap);
+  if (rc) return rc;
+  sf->fixed_scratch = p;
+  sf->fixed_scratch_bytes = cap;
+  rc = launch_reduce(sf, unit, leafdata, rootdata, op, stream);
+  sf->fixed_scratch = nullptr;
+  sf->fixed_scratch_bytes = 0;
+  if (rc) return rc;
+  push_pending(sf, 1, unit, op, rootdata, leafdata, nullptr);
+  return SF_OK;
+}
+
 extern "C" int sf_reduce_end(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
                              hipStream_t stream) {
   (void)stream;
@@ -260,6 +288,7 @@ extern "C" const char *sf_error_string(int code) {
     case SF_ERR_OOM: return "out of memory";
     case SF_ERR_MISMATCH: return "end does not match a pending begin";
     case SF_ERR_BUSY: return "the same operation on the same buffers is already pending";
+    case SF_ERR_SCRATCH: return "the operation needs more scratch than the fixed buffer of the allocation-free call";
     default: return "unknown error";
   }
 }

@@ -28,6 +28,7 @@ constexpr int kHotLdsBytes = 32768;  // LDS budget for the accumulators, default
 constexpr int kReduceGrid = 512;     // grid of the persistent atomic Reduce (measured best)
 constexpr int kFetchGrid = 1024;     // grid of the persistent atomic FetchAndOp (measured best)
 constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
+constexpr size_t kMaxPending = 64;   // pending begin/end pairs reserved per SF
 // Partitioned deterministic path for large SFs (two fully coalesced passes
 // through a window-major scratch copy of the leaves):
 constexpr int kStageThreads = 1024;      // threads per block of the staged kernels
@@ -209,6 +210,10 @@ struct sf_s {
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
   std::vector<void *> retired;
+  // set only for the duration of an allocation-free call: scratch comes from
+  // this fixed device buffer (one per device) and nothing is allocated
+  void *fixed_scratch = nullptr;
+  size_t fixed_scratch_bytes = 0;
   std::vector<sfi::Pending> pending;
   std::mutex mu;
 };
@@ -221,6 +226,18 @@ int upload(sf_s *sf);
 void free_device(sf_s *sf);
 int set_hip_error(hipError_t e);
 int ensure_scratch(sf_s *sf, size_t bytes);
+// Scratch of at least `bytes` for the operation being enqueued: the fixed
+// buffer during an allocation-free call (SF_ERR_SCRATCH when it is too
+// small), else the SF's own buffer, grown with ensure_scratch.
+int acquire_scratch(sf_s *sf, size_t bytes, void **out);
+// Whether `bytes` of scratch can be had without failing: always, unless an
+// allocation-free call is in progress and the fixed buffer is smaller.
+inline bool scratch_fits(const sf_s *sf, size_t bytes) {
+  return sf->fixed_scratch == nullptr || bytes <= sf->fixed_scratch_bytes;
+}
+// Device address and size of the calling device's fixed scratch buffer
+// (implemented in sf_noalloc.hip).
+int fixed_scratch(void **ptr, size_t *bytes);
 
 // kernel launchers implemented in sf_kernels.hip
 int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, hipStream_t st);

@@ -572,7 +572,8 @@ template <typename T, int OP>
 static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)sizeof(T) * bs) >= 0)
+  const size_t ub = sizeof(T) * (size_t)bs;
+  if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)ub) >= 0 && scratch_fits(sf, part_scratch_need(sf, ub)))
     return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
@@ -580,6 +581,17 @@ static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st
       hipLaunchKernelGGL((k_det_replace<T>), dim3(nblocks(T_ * bs)), dim3(kBlock), 0, st, d.troot, (int)T_, d.toff,
                          d.sl, leaf, root, bs);
     return check_launch();
+  }
+  // scratch of the chunk levels first, so that nothing is enqueued when it
+  // cannot be had
+  T *buf[2] = {nullptr, nullptr};
+  if (!h.levels.empty()) {
+    const size_t len = (size_t)std::max<int64_t>(h.scratch_len, 1) * bs;
+    void *s = nullptr;
+    int rc = acquire_scratch(sf, 2 * len * sizeof(T), &s);
+    if (rc) return rc;
+    buf[0] = (T *)s;
+    buf[1] = (T *)s + len;
   }
   // all small classes in one launch, NV elements per thread when the unit
   // and the buffers allow vector accesses
@@ -601,10 +613,6 @@ static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st
   }
   // chunk levels
   if (!h.levels.empty()) {
-    const size_t need = 2 * (size_t)std::max<int64_t>(h.scratch_len, 1) * bs * sizeof(T);
-    int rc = ensure_scratch(sf, need);
-    if (rc) return rc;
-    T *buf[2] = {(T *)sf->scratch, (T *)sf->scratch + (size_t)std::max<int64_t>(h.scratch_len, 1) * bs};
     for (size_t k = 0; k < h.levels.size(); k++) {
       const int nch = (int)h.levels[k].chunks.size();
       const T *src = k == 0 ? leaf : buf[(k - 1) % 2];
@@ -628,7 +636,9 @@ template <typename T, int OP>
 static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
-  if (h.part_red_atomic && stage_class((int64_t)sizeof(T) * bs) >= 0) return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
+  const size_t ub = sizeof(T) * (size_t)bs;
+  if (h.part_red_atomic && stage_class((int64_t)ub) >= 0 && scratch_fits(sf, part_scratch_need(sf, ub)))
+    return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
   const int ntiles = (int)h.tiles.size();
   const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kReduceGrid);
   const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
@@ -641,9 +651,10 @@ static int reduce_maxloc_atomic(sf_s *sf, const Pair *leaf, Pair *root, int bs, 
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const int T_ = (int)h.troot.size();
-  int rc = ensure_scratch(sf, (size_t)std::max(T_, 1) * bs * sizeof(double));
+  void *s = nullptr;
+  int rc = acquire_scratch(sf, (size_t)std::max(T_, 1) * bs * sizeof(double), &s);
   if (rc) return rc;
-  double *saved = (double *)sf->scratch;
+  double *saved = (double *)s;
   const unsigned g = (unsigned)h.tiles.size();
   hipLaunchKernelGGL(k_maxloc_save, dim3(nblocks((int64_t)T_ * bs)), dim3(kBlock), 0, st, d.troot, T_, root, saved, bs);
   hipLaunchKernelGGL((k_maxloc_stream<0>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx, d.lidx, leaf, root, bs);
@@ -733,9 +744,10 @@ static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream
   const int nch = (int)h.fo_chunks.size();
   const int nlarge = (int)h.large.size();
   if (nch) {
-    int rc = ensure_scratch(sf, (size_t)nch * bs * sizeof(T));
+    void *s = nullptr;
+    int rc = acquire_scratch(sf, (size_t)nch * bs * sizeof(T), &s);
     if (rc) return rc;
-    T *sums = (T *)sf->scratch;
+    T *sums = (T *)s;
     hipLaunchKernelGGL((k_fop_chunk_sum<T>), dim3(nblocks((int64_t)nch * 64)), dim3(kBlock), 0, st, d.fo_chunks, nch,
                        d.sl, leaf, sums, bs);
     hipLaunchKernelGGL((k_fop_root_scan<T>), dim3((unsigned)((nlarge * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,

@@ -936,17 +936,25 @@ static int sp_check() {
 // is set once rather than on every launch.
 static int allow_lds(const void *fn, size_t bytes) {
   if (bytes <= 65536) return SF_OK;
+  // a fixed table, so that no call allocates host memory either (a full
+  // table only means the attribute is set again on each launch)
+  struct Grant {
+    const void *fn;
+    int dev;
+    size_t bytes;
+  };
   static std::mutex mu;
-  static std::vector<std::pair<std::pair<const void *, int>, size_t>> granted;
+  static Grant granted[256];
+  static int ngranted = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return set_hip_error(e);
   std::lock_guard<std::mutex> g(mu);
-  for (auto &x : granted)
-    if (x.first.first == fn && x.first.second == dev && x.second >= bytes) return SF_OK;
+  for (int k = 0; k < ngranted; k++)
+    if (granted[k].fn == fn && granted[k].dev == dev && granted[k].bytes >= bytes) return SF_OK;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return set_hip_error(e);
-  granted.push_back({{fn, dev}, bytes});
+  if (ngranted < 256) granted[ngranted++] = {fn, dev, bytes};
   return SF_OK;
 }
 
@@ -1053,10 +1061,11 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   const DevPlan::Stage &ds = d.sp[cls];
   const size_t lvl = (size_t)std::max<int64_t>(h.scratch_len, 1) * ub;
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
-  int rc = ensure_scratch(sf, main_bytes + 2 * lvl);
+  void *s = nullptr;
+  int rc = acquire_scratch(sf, main_bytes + 2 * lvl, &s);
   if (rc) return rc;
-  T *scr = (T *)sf->scratch;
-  T *buf[2] = {(T *)((char *)sf->scratch + main_bytes), (T *)((char *)sf->scratch + main_bytes + lvl)};
+  T *scr = (T *)s;
+  T *buf[2] = {(T *)((char *)s + main_bytes), (T *)((char *)s + main_bytes + lvl)};
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   const PassBLds pl = passb_lds(hs, ub);
@@ -1095,11 +1104,12 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
   // scratch: window-major leaf units, then run totals and run bases (2 per window)
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
   const size_t runs_bytes = ((size_t)2 * gw * ub + 255) / 256 * 256;
-  int rc = ensure_scratch(sf, main_bytes + (det ? 2 * runs_bytes : 0));
+  void *s = nullptr;
+  int rc = acquire_scratch(sf, main_bytes + (det ? 2 * runs_bytes : 0), &s);
   if (rc) return rc;
-  T *scr = (T *)sf->scratch;
-  T *rtot = (T *)((char *)sf->scratch + main_bytes);
-  T *rbase = (T *)((char *)sf->scratch + main_bytes + runs_bytes);
+  T *scr = (T *)s;
+  T *rtot = (T *)((char *)s + main_bytes);
+  T *rbase = (T *)((char *)s + main_bytes + runs_bytes);
   const PassBLds pl = passb_lds(hs, ub);
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;

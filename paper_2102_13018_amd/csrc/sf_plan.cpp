@@ -611,6 +611,18 @@ int ensure_scratch(sf_s *sf, size_t bytes) {
   return SF_OK;
 }
 
+int acquire_scratch(sf_s *sf, size_t bytes, void **out) {
+  if (sf->fixed_scratch) {
+    if (bytes > sf->fixed_scratch_bytes) return SF_ERR_SCRATCH;
+    *out = sf->fixed_scratch;
+    return SF_OK;
+  }
+  int rc = ensure_scratch(sf, bytes);
+  if (rc) return rc;
+  *out = sf->scratch;
+  return SF_OK;
+}
+
 int upload(sf_s *sf) {
   free_device(sf);
   HostPlan &hp = sf->hp;

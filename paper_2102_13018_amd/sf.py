@@ -21,14 +21,15 @@ SF_KIND_BCAST, SF_KIND_REDUCE = 0, 1
 SF_PATTERN_GENERIC, SF_PATTERN_CONTIGUOUS, SF_PATTERN_3D = 0, 1, 2
 ERRORS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_DUP_LEAF", -3: "SF_ERR_NOT_SETUP",
           -4: "SF_ERR_UNSUPPORTED", -5: "SF_ERR_HIP", -6: "SF_ERR_OOM", -7: "SF_ERR_MISMATCH",
-          -8: "SF_ERR_BUSY"}
+          -8: "SF_ERR_BUSY", -9: "SF_ERR_SCRATCH"}
+SF_NOALLOC_SCRATCH_BYTES = 64 << 20
 OPS = {"replace": SF_REPLACE, "sum": SF_SUM, "max": SF_MAX, "min": SF_MIN, "maxloc": SF_MAXLOC}
 MODES = {"auto": SF_REDUCE_AUTO, "atomic": SF_REDUCE_ATOMIC, "deterministic": SF_REDUCE_DETERMINISTIC}
 ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16}
 
 EXPORTS = [
     "sf_create", "sf_setup", "sf_set_reduce_mode", "sf_bcast_begin", "sf_bcast_end",
-    "sf_reduce_begin", "sf_reduce_end", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
+    "sf_reduce_begin", "sf_reduce_end", "sf_reduce_begin_noalloc", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
     "sf_batch_create", "sf_batch_launch", "sf_batch_launch_separate", "sf_batch_graph_capture",
     "sf_batch_graph_launch", "sf_batch_autotune", "sf_batch_get_config", "sf_batch_set_config",
     "sf_batch_destroy", "sf_get_info", "sf_get_segment", "sf_error_string", "sf_last_hip_error",
@@ -99,7 +100,8 @@ def lib():
         L.sf_create.argtypes = [i64, i64, p, i32, p, i32, ctypes.POINTER(p)]
         L.sf_setup.argtypes = [p, ctypes.POINTER(SfSetupOpts)]
         L.sf_set_reduce_mode.argtypes = [p, i32]
-        for name in ("sf_bcast_begin", "sf_bcast_end", "sf_reduce_begin", "sf_reduce_end"):
+        for name in ("sf_bcast_begin", "sf_bcast_end", "sf_reduce_begin", "sf_reduce_end",
+                     "sf_reduce_begin_noalloc"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, i32, p]
         for name in ("sf_fetch_and_op_begin", "sf_fetch_and_op_end"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, p, i32, p]
@@ -206,6 +208,10 @@ class StarForest:
     def reduce_begin(self, unit, leaf, root, op="sum", stream=None):
         check(lib().sf_reduce_begin(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op), _stream(stream)),
               "sf_reduce_begin")
+
+    def reduce_begin_noalloc(self, unit, leaf, root, op="sum", stream=None):
+        check(lib().sf_reduce_begin_noalloc(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op),
+                                            _stream(stream)), "sf_reduce_begin_noalloc")
 
     def reduce_end(self, unit, leaf, root, op="sum", stream=None):
         check(lib().sf_reduce_end(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op), _stream(stream)),
