@@ -177,11 +177,16 @@ def build_spmv_ops(torch, S, inputs, g):
     return sf, ops, direct, data
 
 
-def time_ops(torch, ops, steps, warmup):
+def time_ops(torch, ops, steps, warmup, flush=None):
     """Warm up, then time exactly `steps` steps; every op is bracketed by
-    events on the current stream (the stream the library launches on)."""
+    events on the current stream (the stream the library launches on).  With
+    `flush` (a >= 1 GiB device buffer), the buffer is overwritten before
+    every op, outside its events: L2 and the 256 MB Infinity Cache hold none
+    of the op's data when it starts (cold)."""
     for _ in range(warmup):
         for op in ops:
+            if flush is not None:
+                flush.fill_(1.0)
             op.fn()
     torch.cuda.synchronize()
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
@@ -189,6 +194,8 @@ def time_ops(torch, ops, steps, warmup):
     t0 = time.perf_counter()
     for s in range(steps):
         for k, op in enumerate(ops):
+            if flush is not None:
+                flush.fill_(1.0)
             ev[s][k][0].record()
             op.fn()
             ev[s][k][1].record()
@@ -200,26 +207,20 @@ def time_ops(torch, ops, steps, warmup):
     return wall
 
 
-def cold_ops(torch, ops, reps=10):
-    """Each op timed alone after flushing the 256 MB Infinity Cache (a 1 GiB
-    fill between reps); median of `reps` event-timed runs."""
-    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+def warm_ops(torch, ops, steps, warmup):
+    """The step's ops back to back without flushes (the Infinity Cache keeps
+    what the previous op left): a labelled side row."""
+    for o in ops:
+        o.times = []
+    wall = time_ops(torch, ops, steps, warmup)
     out = {}
-    for op in ops:
-        op.fn()
-        ts = []
-        for _ in range(reps):
-            flush.fill_(1.0)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            op.fn()
-            e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        med = float(np.median(ts))
-        out[op.name] = {"us": round(med * 1e3, 1), "GBps": round(op.nbytes / med / 1e6, 1)}
-    del flush
-    return out
+    for o in ops:
+        med = float(np.median(o.times))
+        out[o.name] = {"us": round(med * 1e3, 1), "GBps": round(o.nbytes / med / 1e6, 1),
+                       "frac_peak": round(o.nbytes / med / 1e6 / HBM_PEAK_GBS, 4)}
+    step_bytes = sum(o.nbytes for o in ops)
+    return {"cache": "warm (ops back to back, no flush)", "value": round(step_bytes / (wall / steps) / 1e9, 1),
+            "ms_per_step": round(wall * 1e3 / steps, 3), "ops": out}
 
 
 def copy_ceiling(torch, nbytes=1 << 31):
@@ -240,10 +241,13 @@ def copy_ceiling(torch, nbytes=1 << 31):
     return round(2 * nbytes / float(np.min(ts)) / 1e6, 1)
 
 
-def cpu_baseline(g, budget_s=12.0):
+def cpu_baseline(g, budget_s=8.0):
     """The oracle, as it stands, on the same SF: Bcast, Reduce SUM and
-    FetchAndOp (sequential C, one thread).  Runs ops until the budget is
-    spent (whole rounds); reports algorithmic bytes / time."""
+    FetchAndOp, in two builds -- the OpenMP variants (leaves split among the
+    threads for Bcast, roots for Reduce and FetchAndOp, each root's leaves in
+    leaf order: the same bits) on every host thread it is given, and the
+    sequential definitions on one.  Each leg runs whole rounds of the three
+    ops until its budget is spent; reports algorithmic bytes / time."""
     import oracle
     rng = np.random.default_rng(99)
     L, R = g.nleaves, g.nroots
@@ -252,22 +256,33 @@ def cpu_baseline(g, budget_s=12.0):
     xr = rng.standard_normal(R)
     xl = rng.standard_normal(L)
     root0 = np.concatenate([[0], np.cumsum(deg)[:-1]]).astype(np.int64)
-    jobs = [("bcast_replace_f64", lambda: oracle.bcast(R, g.iroot, None, xr, xl), L * 8 + Rt * 8 + 4 * L),
-            ("reduce_sum_f64", lambda: oracle.reduce(R, g.iroot, None, xl, xr), L * 8 + 2 * Rt * 8 + 4 * L),
-            ("fetch_and_op_i64", lambda: oracle.fetch_and_op(R, g.iroot, None, root0, np.ones(L, np.int64),
-                                                             np.zeros(L, np.int64)),
-             2 * L * 8 + 2 * Rt * 8 + 4 * L)]
-    tot_b, tot_t, rounds = 0, 0.0, 0
-    while tot_t < budget_s:
-        for name, fn, nb in jobs:
-            t0 = time.perf_counter()
-            fn()
-            tot_t += time.perf_counter() - t0
-            tot_b += nb
-        rounds += 1
-    return {"value": round(tot_b / tot_t / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rounds} rounds of (" + ", ".join(j[0] for j in jobs) + ") on the full spmv_ghost SF, "
-                      f"sequential C oracle, {tot_t:.1f} s of CPU time",
+    ones, zeros = np.ones(L, np.int64), np.zeros(L, np.int64)
+    nb = {"bcast": L * 8 + Rt * 8 + 4 * L, "reduce": L * 8 + 2 * Rt * 8 + 4 * L,
+          "fetch": 2 * L * 8 + 2 * Rt * 8 + 4 * L}
+
+    def leg(bcast, reduce, fetch):
+        jobs = [("bcast_replace_f64", lambda: bcast(R, g.iroot, None, xr, xl), nb["bcast"]),
+                ("reduce_sum_f64", lambda: reduce(R, g.iroot, None, xl, xr), nb["reduce"]),
+                ("fetch_and_op_i64", lambda: fetch(R, g.iroot, None, root0, ones, zeros), nb["fetch"])]
+        tot_b, tot_t, rounds = 0, 0.0, 0
+        while tot_t < budget_s:
+            for name, fn, n in jobs:
+                t0 = time.perf_counter()
+                fn()
+                tot_t += time.perf_counter() - t0
+                tot_b += n
+            rounds += 1
+        return round(tot_b / tot_t / 1e9, 4), rounds, tot_t
+
+    threads = oracle.omp_threads()
+    v_omp, r_omp, t_omp = leg(oracle.bcast_omp, oracle.reduce_omp, oracle.fetch_and_op_omp)
+    v_seq, r_seq, t_seq = leg(oracle.bcast, oracle.reduce, oracle.fetch_and_op)
+    ops = "(bcast_replace_f64, reduce_sum_f64, fetch_and_op_i64)"
+    return {"value": v_omp, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{r_omp} rounds of {ops} on the full spmv_ghost SF, OpenMP oracle on {threads} threads, "
+                      f"{t_omp:.1f} s",
+            "sequential": {"value": v_seq, "unit": "GB/s", "cores": 1,
+                           "sample": f"{r_seq} rounds of {ops}, sequential C oracle, {t_seq:.1f} s"},
             "cpu": cpu_model(), "host_threads": os.cpu_count()}
 
 
@@ -421,9 +436,9 @@ def batch_row(torch, S, inputs, steps):
             "device": out, "host_wall_us": wall}
 
 
-def autograd_row(torch, S, inputs, steps):
+def autograd_row(torch, S, inputs, steps, g=None):
     from paper_2102_13018_amd import autograd as A
-    g = inputs.knn_graph(seed=5)
+    g = g if g is not None else inputs.knn_graph(seed=5)
     dev = torch.device("cuda")
     rng = np.random.default_rng(6)
     sf = S.StarForest(g.nroots, g.iroot, None, None).setup(reduce_mode="deterministic")
@@ -452,6 +467,46 @@ def autograd_row(torch, S, inputs, steps):
     return {"workload": f"knn(npoints={g.nroots}, k=8) fp32 x16, 3-layer checkpointed chain",
             "step_us": round(ms * 1e3, 1), "sf_alg_bytes": sf_bytes,
             "sf_GBps_lower_bound": round(sf_bytes / ms / 1e6, 1)}
+
+
+def build_knn_ops(torch, S, g):
+    """The differentiable gather/scatter workload's two SF ops alone: SFBcast
+    REPLACE and the deterministic SFReduce SUM of fp32 x 16 units (64 bytes)
+    on the 1M-point k-NN graph (8M leaves, in-degree 0..20)."""
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(7)
+    L, R = g.nleaves, g.nroots
+    deg = np.bincount(g.iroot, minlength=R)
+    Rt = int((deg > 0).sum())
+    sf = S.StarForest(R, g.iroot, None, None).setup(reduce_mode="deterministic")
+    root = torch.from_numpy(rng.standard_normal((R, 16)).astype(np.float32)).to(dev)
+    leaf = torch.from_numpy(rng.standard_normal((L, 16)).astype(np.float32)).to(dev)
+    leaf_out = torch.empty_like(leaf)
+    root_acc = root.clone()
+    u = S.SfUnit(S.SF_F32, 16)
+    ub = 64
+    ops = [Op("knn_bcast_f32x16", lambda: sf.bcast(root, leaf_out, "replace", unit=u), L * ub + Rt * ub + 4 * L,
+              "k_bcast_move"),
+           Op("knn_reduce_sum_f32x16_det", lambda: sf.reduce(leaf, root_acc, "sum", unit=u),
+              L * ub + 2 * Rt * ub + 4 * L, "k_det_small_all")]
+    return sf, ops, (root, leaf, leaf_out, root_acc)
+
+
+def knn_row(torch, S, g, steps, flush, copy_gbps):
+    """Each op alone, cold (flush before every run), with its roofline."""
+    sf, ops, keep = build_knn_ops(torch, S, g)
+    time_ops(torch, ops, steps, 2, flush=flush)
+    out = {}
+    for o in ops:
+        avg = float(np.mean(o.times))
+        ach = o.nbytes / avg / 1e6
+        out[o.name] = {"us": round(float(np.median(o.times)) * 1e3, 1), "avg_us": round(avg * 1e3, 1),
+                       "alg_MB": round(o.nbytes / 1e6, 1), "GBps": round(ach, 1),
+                       "frac_peak": round(ach / HBM_PEAK_GBS, 4),
+                       "frac_copy_ceiling": round(ach / copy_gbps, 4) if copy_gbps else None,
+                       "kernel": o.kernels, "traffic": measured_traffic(o.name)}
+    return {"workload": f"knn(npoints={g.nroots}, k=8) fp32 x16 (64-byte units), each op alone",
+            "cache": "cold (1 GiB write before every op)", "ops": out}
 
 
 def partition_sweep(torch, S, inputs, steps):
@@ -530,50 +585,62 @@ def main():
     sf, ops, direct, data = build_spmv_ops(torch, S, inputs, g)
     if args.profile_op:
         names = args.profile_op.split(",")
-        ops = [o for o in ops + direct if o.name in names]
-        assert len(ops) == len(names), f"unknown op in {args.profile_op}"
-        time_ops(torch, ops, args.steps, args.warmup)
-        for o in ops:
+        pick = [o for o in ops + direct if o.name in names]
+        if len(pick) < len(names):
+            gk = inputs.knn_graph(seed=5)
+            _, kops, keep = build_knn_ops(torch, S, gk)
+            pick += [o for o in kops if o.name in names]
+        assert len(pick) == len(names), f"unknown op in {args.profile_op}"
+        time_ops(torch, pick, args.steps, args.warmup)
+        for o in pick:
             log(f"{o.name}: median {np.median(o.times) * 1e3:.1f} us over {len(o.times)} launches")
         return
 
+    # the step, cold: the 256 MB Infinity Cache and the L2s are flushed by a
+    # 1 GiB write before every op (outside the op's events)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    wall = time_ops(torch, ops, args.steps, args.warmup)
+    wall = time_ops(torch, ops, args.steps, args.warmup, flush=flush)
     step_bytes = sum(o.nbytes for o in ops)
-    ms_per_step = wall * 1e3 / args.steps
-    value = step_bytes / (wall / args.steps) / 1e9
+    dev_ms = float(np.mean([sum(o.times[s] for o in ops) for s in range(args.steps)]))
+    value = step_bytes / dev_ms / 1e6
     per_op = {}
     for o in ops:
         med = float(np.median(o.times))
         per_op[o.name] = {"us": round(med * 1e3, 1), "alg_MB": round(o.nbytes / 1e6, 1),
                           "GBps": round(o.nbytes / med / 1e6, 1),
                           "frac_peak": round(o.nbytes / med / 1e6 / HBM_PEAK_GBS, 4)}
-        log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
+        log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s (cold)")
+    copy_gbps = copy_ceiling(torch)
     # dominant op: the largest share of step time; one launch of it is one
     # begin/end pair, i.e. the sequence of kernels named in "kernel"
     dom = max(ops, key=lambda o: float(np.mean(o.times)))
     avg_ms = float(np.mean(dom.times))
+    achieved = dom.nbytes / avg_ms / 1e6
     roofline = {"bound": "hbm", "kernel": dom.kernels, "op": dom.name,
-                "achieved": round(dom.nbytes / avg_ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom.nbytes / avg_ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.name),
-                "alg_bytes_per_launch": dom.nbytes,
-                "avg_launch_us": round(avg_ms * 1e3, 1)}
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom.name),
+                "alg_bytes_per_launch": dom.nbytes, "avg_launch_us": round(avg_ms * 1e3, 1),
+                "cache": "cold", "copy_ceiling_GBps": copy_gbps,
+                "frac_of_copy_ceiling": round(achieved / copy_gbps, 4)}
     out = {"metric": "effective HBM GB/s (unit data + indices) for SFBcast/SFReduce vs peak; batched vs per-SF time",
            "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+           "ms_per_step": round(dev_ms, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
-                      "cache": "warm (ops back to back; see ops_cold_cache)",
+                      "cache": "cold: a 1 GiB write flushes L2 and the Infinity Cache before every op; "
+                               "ms_per_step sums the ops' event times, the flushes lie outside them "
+                               "(warm numbers: ops_warm)",
+                      "wall_ms_per_step_with_flushes": round(wall * 1e3 / args.steps, 3),
                       "setup_s": round(data["setup_s"], 2), "parallelism": "single-gpu"},
-           "ops": per_op, "roofline": roofline}
+           "ops": per_op, "roofline": roofline, "copy_ceiling_GBps": copy_gbps,
+           "value_vs_copy_ceiling": round(value / copy_gbps, 4)}
     if not args.no_rows:
         # beside the step (after it, so that a profile of `--no-rows` sees the
-        # step's kernels only): cold-cache op times, a copy ceiling, the direct
-        # atomic kernels, and the halo / batch / autograd rows
-        out["ops_cold_cache"] = cold_ops(torch, ops)
-        out["copy_ceiling_GBps"] = copy_ceiling(torch)
-        out["value_vs_copy_ceiling"] = round(value / out["copy_ceiling_GBps"], 4)
+        # step's kernels only): the warm step, the direct atomic kernels, and
+        # the small / halo / batch / k-NN / autograd rows
+        out["ops_warm"] = warm_ops(torch, ops, args.steps, args.warmup)
         time_ops(torch, direct, max(5, args.steps // 2), 2)
         direct_row = {}
         for o in direct:
@@ -582,13 +649,26 @@ def main():
                                   "kernel": o.kernels, "traffic": measured_traffic(o.name)}
             log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
         out["row_direct_atomic"] = direct_row
-        for name, fn in (("small", small_row), ("halo", halo_row), ("batch", batch_row),
-                         ("autograd", autograd_row)):
+        del sf, ops, direct, data
+        for name, fn in (("small", small_row), ("halo", halo_row), ("batch", batch_row)):
             try:
                 out[f"row_{name}"] = fn(torch, S, inputs, args.steps)
             except Exception as e:  # a row that cannot run is reported, not hidden
                 out[f"row_{name}"] = {"error": repr(e)}
             log(f"row {name}: {out[f'row_{name}']}")
+        gk = None
+        try:
+            gk = inputs.knn_graph(seed=5)
+            out["row_knn"] = knn_row(torch, S, gk, args.steps, flush, copy_gbps)
+        except Exception as e:
+            out["row_knn"] = {"error": repr(e)}
+        log(f"row knn: {out['row_knn']}")
+        try:
+            out["row_autograd"] = autograd_row(torch, S, inputs, args.steps, gk)
+        except Exception as e:
+            out["row_autograd"] = {"error": repr(e)}
+        log(f"row autograd: {out['row_autograd']}")
+    del flush
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)
     print(json.dumps(out), flush=True)

@@ -112,6 +112,13 @@ typedef struct {
                            leaves and from 2^20 otherwise, the atomic FetchAndOp from 2^20),
                            1 always, 2 never.  Deterministic results are identical either way;
                            atomic results meet the same bar either way. */
+  int32_t hot_path;     /* partitioned SFs whose leaf order is their segment order: 1 keeps the
+                           leaves of the roots of highest degree (at least 2 per 8192 leaves on
+                           average, at most 4096 roots) in leaf order -- per-tile partial results
+                           combined per root -- for FetchAndOp and every Reduce but the
+                           deterministic FP sum and MAXLOC; 0 (default) and 2 never (measured
+                           no faster on a 16M-leaf Zipf SF).  Results are identical either way
+                           (atomic ones meet the same bar). */
 } sf_setup_opts;
 
 /* Index pattern of one side of one segment (Section 5.2): index(t) for the
@@ -140,6 +147,7 @@ typedef struct {
   int32_t reduce_mode;    /* current sf_reduce_mode */
   int64_t nhot;           /* roots aggregated in LDS by the atomic path */
   int64_t device_bytes;   /* device memory held by the plan */
+  int64_t hot_roots;      /* roots whose leaves stay in leaf order on the partitioned path (hot_path) */
 } sf_info;
 
 /* Error codes. */

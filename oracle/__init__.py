@@ -34,14 +34,18 @@ PW_TOPDOWN, PW_BOTTOMUP = 0, 1
 _lib = None
 
 
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force=True):
-    """Compile liboracle.so with gcc (no fast-math, no FP contraction)."""
-    src = os.path.join(_HERE, "sf_oracle.c")
-    cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
-           "-o", _SO + ".tmp", src, "-lm"]
-    if force or not os.path.exists(_SO):
-        subprocess.check_call(cmd)
-        os.replace(_SO + ".tmp", _SO)
+    """Compile liboracle.so (sequential) and liboracle_omp.so (the same
+    definitions plus their OpenMP variants, for the CPU baseline) with gcc:
+    no fast-math, no FP contraction."""
+    flags = ["-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
+    for so, src, extra in ((_SO, "sf_oracle.c", []), (_SO_OMP, "sf_oracle_omp.c", ["-fopenmp"])):
+        if force or not os.path.exists(so):
+            subprocess.check_call(["gcc", *flags, *extra, "-o", so + ".tmp", os.path.join(_HERE, src), "-lm"])
+            os.replace(so + ".tmp", so)
     return _SO
 
 
@@ -63,6 +67,32 @@ def lib():
         L.orc_pairwise_f32.restype = ctypes.c_float
         _lib = L
     return _lib
+
+
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP build (CPU baseline only)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_SO_OMP):
+            build()
+        L = ctypes.CDLL(_SO_OMP)
+        i64, p, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        L.orc_bcast_omp.argtypes = [i64, i64, p, p, ci, ci, ci, p, p]
+        L.orc_reduce_omp.argtypes = [i64, i64, p, p, ci, ci, ci, p, p]
+        L.orc_fetch_and_op_omp.argtypes = [i64, i64, p, p, ci, ci, ci, p, p, p]
+        for f in (L.orc_bcast_omp, L.orc_reduce_omp, L.orc_fetch_and_op_omp, L.orc_omp_threads):
+            f.restype = ci
+        L.orc_omp_threads.argtypes = []
+        _lib_omp = L
+    return _lib_omp
+
+
+def omp_threads():
+    """Threads the OpenMP variants run on (OMP_NUM_THREADS, else the host's)."""
+    return int(lib_omp().orc_omp_threads())
 
 
 def _ptr(a):
@@ -144,3 +174,48 @@ def pairwise(x, form=PW_TOPDOWN):
     if x.dtype == np.float32:
         return np.float32(lib().orc_pairwise_f32(_ptr(x), x.size, form))
     raise TypeError(x.dtype)
+
+
+# ------------------------------------------------ OpenMP variants (baseline)
+def bcast_omp(nroots, iroot, ilocal, rootdata, leafdata, op="replace"):
+    """bcast() on several host threads; identical results."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    root = np.ascontiguousarray(rootdata)
+    leaf = np.array(leafdata, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) and root.shape[0] == nroots
+    rc = lib_omp().orc_bcast_omp(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                                 _ptr(root), _ptr(leaf))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return leaf
+
+
+def reduce_omp(nroots, iroot, ilocal, leafdata, rootdata, op="sum"):
+    """reduce() on several host threads (roots split among them); identical results."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    leaf = np.ascontiguousarray(leafdata)
+    root = np.array(rootdata, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) and root.shape[0] == nroots
+    rc = lib_omp().orc_reduce_omp(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                                  _ptr(leaf), _ptr(root))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return root
+
+
+def fetch_and_op_omp(nroots, iroot, ilocal, rootdata, leafdata, leafupdate, op="sum"):
+    """fetch_and_op() on several host threads (roots split among them, each
+    root's leaves in leaf order); identical results."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    leaf = np.ascontiguousarray(leafdata)
+    root = np.array(rootdata, copy=True, order="C")
+    upd = np.array(leafupdate, copy=True, order="C")
+    dt, bs = _unit(root)
+    assert _unit(leaf) == (dt, bs) == _unit(upd) and root.shape[0] == nroots
+    rc = lib_omp().orc_fetch_and_op_omp(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), dt, bs, _op(op),
+                                        _ptr(root), _ptr(leaf), _ptr(upd))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return root, upd

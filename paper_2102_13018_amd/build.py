@@ -27,7 +27,10 @@ FLAGS = [
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    # a compilation-unit id named for the file (not hashed from its path), so
+    # that the device code does not depend on where the tree is built
+    cuid = "-cuid=" + os.path.splitext(src)[0]
+    cmd = [HIPCC, *FLAGS, cuid, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

@@ -87,7 +87,7 @@ extern "C" int sf_setup(sf_t sf, const sf_setup_opts *opts) {
   o.use_patterns = 1;
   if (opts) o = *opts;
   if (o.reduce_mode < SF_REDUCE_AUTO || o.reduce_mode > SF_REDUCE_DETERMINISTIC) return SF_ERR_ARG;
-  if (o.partition < 0 || o.partition > 2) return SF_ERR_ARG;
+  if (o.partition < 0 || o.partition > 2 || o.hot_path < 0 || o.hot_path > 2) return SF_ERR_ARG;
   sf->opts = o;
   sf->reduce_mode = o.reduce_mode;
   sf->setup = false;
@@ -261,6 +261,7 @@ extern "C" int sf_get_info(sf_t sf, sf_info *info) {
   info->has_dup_roots = sf->has_dup_roots ? 1 : 0;
   info->nhot = (int64_t)sf->hp.hot_roots.size();
   info->device_bytes = (int64_t)sf->dp.bytes;
+  info->hot_roots = sf->hp.hot ? (int64_t)sf->hp.hx_root.size() : 0;
   return SF_OK;
 }
 

@@ -43,6 +43,12 @@ constexpr int kStageMaxLds = 131072;     // LDS of one staged block (bytes)
 constexpr int64_t kPartitionPlan = 1 << 16;
 constexpr int64_t kPartitionMid = 1 << 19;
 constexpr int64_t kPartitionBig = 1 << 20;
+// Hot roots of the partitioned path: at least this many leaves per pass-A
+// tile on average (fewer and a group costs about what the windows cost),
+// and at most kHotRootsMax of them.
+constexpr int kHotPerTile = 2;
+constexpr int kHotRootsMax = 4096;
+constexpr int kPassATile = 8192;     // pass-A tile (processing positions), both unit-size classes
 
 // --------------------------------------------------------- device structs
 // Pattern of one side of a segment: index(t) = start + i + sy*j + sz*k with
@@ -126,6 +132,27 @@ struct HostPlan {
   // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
   std::vector<DevChunk> fo_chunks;
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
+  // Hot roots of the partitioned path: roots with at least kHotPerTile leaves
+  // per pass-A tile on average.  Their leaves stay in leaf order: pass A
+  // combines each tile's leaves of one hot root (a "group": one per tile and
+  // hot root present) into one value, a scan kernel combines the groups of a
+  // root in tile order, and FetchAndOp's pass C gives every hot leaf its
+  // group's base plus its exclusive prefix inside the group.  Cold roots take
+  // the windows, which are packed cold roots first: windows [0, wcold) of a
+  // stage hold no hot root.
+  bool hot = false;                 // the hot path is planned
+  std::vector<int32_t> hx_root;     // [H] root id of hot root h
+  std::vector<uint16_t> hx_pos;     // per hot entry, tile-major, grouped by hot root, in leaf order inside a
+                                    //   group: tile offset (13 bits) | 0x8000 at a group's first entry
+  std::vector<int32_t> hx_e0;       // [ntiles + 1] first hot entry of each pass-A tile
+  std::vector<int32_t> hx_grp0;     // [ntiles + 1] first group of each pass-A tile
+  std::vector<int32_t> hx_rfirst;   // [H + 1] first group of each hot root in root-major order
+  std::vector<int32_t> hx_rpos;     // per group (tile-major): its index in root-major order (tile order
+                                    //   inside a root); group values are stored root-major
+  std::vector<uint16_t> hx_tg;      // [ntiles * kStageThreads] groups that start before the first entry of each
+                                    //   thread of a tile's hot phase (thread t takes K = ceil(entries /
+                                    //   kStageThreads) consecutive entries from t * K)
+  int32_t hx_maxgrp = 0;            // most groups of a hot root
   // partitioned deterministic path: one plan per unit-size class
   // (class 0: units of <= 8 bytes, class 1: units of 9..16 bytes)
   bool part = false;  // the partition plans are built (the deterministic FetchAndOp uses them)
@@ -134,14 +161,17 @@ struct HostPlan {
     int32_t ta = 0, cap = 0;          // pass-A tile and window capacity, in units
     int32_t maxbig = 0;               // most level-0 chunks in one window
     int32_t maxrun = 0;               // most slot runs in one pass-A tile
+    int32_t wcold = 0;                // windows [0, wcold) hold only cold roots (all, without a hot path)
+    int32_t nspan_cold = 0;           // spanning roots in those windows (listed first)
     std::vector<DevSWin> win;
     std::vector<DevSRoot> sroot;      // whole roots, window-major (by degree class inside a window)
     std::vector<DevWChunk> wchunk;    // chunks of large roots, window-major, in chunk order
     std::vector<uint16_t> lpos;       // [L] by scratch slot: sorted position minus window start (< 2^14)
     std::vector<uint16_t> pa_loc;     // [L] pass-A tile-major, by increasing scratch slot in a tile: the
                                       //     tile-local processing offset of that leaf (13 bits) | 0x8000 at
-                                      //     a run start | 0x2000 if the slot lies in a run of a root that
-                                      //     spans windows | 0x4000 if that run continues into the next
+                                      //     a run start | 0x2000 if the slot lies in a run of a cold root that
+                                      //     spans windows | 0x4000 if that run continues into the next;
+                                      //     0x4000 without 0x2000: the leaf of a hot root
     std::vector<int32_t> pa_run;      // per run of consecutive slots: first slot minus its tile position
     std::vector<int32_t> pa_run0;     // [ntiles + 1] first run of each tile
     std::vector<int32_t> pa_runw;     // per run: its window
@@ -176,6 +206,8 @@ struct DevPlan {
     int32_t *pa_runw = nullptr, *span_first = nullptr, *span_slot = nullptr, *span_root = nullptr;
     uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
+  int32_t *hx_root = nullptr, *hx_e0 = nullptr, *hx_grp0 = nullptr, *hx_rfirst = nullptr, *hx_rpos = nullptr;
+  uint16_t *hx_pos = nullptr, *hx_tg = nullptr;
 };
 
 struct Pending {

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "sf_det_kernels.h"
+#include "sf_hot.h"
 
 namespace sfi {
 
@@ -87,8 +88,13 @@ struct MoveFix {
 #define SP_MOVE_ARGS                                                                                      \
   const uint16_t *__restrict__ pa_loc, const int32_t *__restrict__ pa_run0, const int32_t *__restrict__ pa_run, \
       const int32_t *__restrict__ tile_leaf0, const int32_t *__restrict__ pa_slot, int64_t L, int ta,           \
-      Word *__restrict__ leaf, Word *__restrict__ scratch, int W, int run_off, int run_cap, MoveFix fx
-template <typename Word, int DIR, int P, int FIX>
+      Word *__restrict__ leaf, Word *__restrict__ scratch, int W, int run_off, int run_cap, MoveFix fx,      \
+      HotArgs ha, int bs
+// HS: the hot-root phase (HotNone: none).  With one, the leaves of hot
+// roots (0x4000 alone in pa_loc) are not moved: pass A combines them per
+// group (HOT_TOTALS, HOT_PREFIX), pass C writes their fetched values
+// (HOT_APPLY).
+template <typename Word, int DIR, int P, int FIX, typename HS>
 __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t grp[kMoveGroups];
@@ -190,6 +196,8 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
   for (int k = 0; k < P; k++) {
     const int64_t slot = sl[k];
     if (slot < 0 || slot >= L) continue;
+    if constexpr (HS::mode != HOT_NONE)
+      if ((lv[k] & 0x6000) == 0x4000) continue;  // a hot root's leaf: the hot phase takes it
     const int64_t s = slot * W;
     const int src = (lv[k] & 0x1fff);
     int64_t fe = -1;  // FIX: first rbase element of the slot's run, if it has one
@@ -227,6 +235,13 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
       }
     }
   }
+  if constexpr (HS::mode != HOT_NONE) {
+    using HT = typename HS::type;
+    static_assert(DIR == 0 ? HS::mode != HOT_APPLY : HS::mode == HOT_APPLY, "hot phase of the pass");
+    // (pass A: the tile in LDS is complete since the barriers before the
+    // moves, which only read it; pass C writes positions no move writes)
+    hot_phase<HS>(ha, tile, p0, bs, leaf0, pa_slot, reinterpret_cast<HT *>(smem), reinterpret_cast<HT *>(leaf));
+  }
   if (DIR == 1 && leaf0 >= 0) {  // leaf units are written once: streaming stores
     __syncthreads();
 #pragma unroll 8
@@ -236,15 +251,15 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
 
 // Tiles of units up to 8 bytes take 64 KB of LDS; two blocks share a CU
 // when the kernel also stays within 64 VGPRs (8 waves per SIMD).
-template <typename Word, int DIR, int P, int FIX>
+template <typename Word, int DIR, int P, int FIX, typename HS>
 __global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sp_move2(SP_MOVE_ARGS) {
-  sp_move_body<Word, DIR, P, FIX>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
-                                  run_cap, fx);
+  sp_move_body<Word, DIR, P, FIX, HS>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
+                                      run_cap, fx, ha, bs);
 }
-template <typename Word, int DIR, int P, int FIX>
+template <typename Word, int DIR, int P, int FIX, typename HS>
 __global__ __launch_bounds__(kStageThreads) void k_sp_move(SP_MOVE_ARGS) {
-  sp_move_body<Word, DIR, P, FIX>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
-                                  run_cap, fx);
+  sp_move_body<Word, DIR, P, FIX, HS>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
+                                      run_cap, fx, ha, bs);
 }
 #undef SP_MOVE_ARGS
 
@@ -422,77 +437,6 @@ struct OrderFree {
       OP == OP_MAX || OP == OP_MIN || OP == OP_MAXLOC || (OP == OP_SUM && std::is_integral<V>::value);
   static constexpr bool idempotent = OP != OP_SUM;
 };
-
-// v from the lane that the DPP control CTRL selects, for every 32-bit word
-// of V (a pair's padding word is not moved).
-template <int CTRL, typename V>
-__device__ __forceinline__ V dpp_mov(V v) {
-  constexpr int N = std::is_same<V, Pair>::value ? 3 : (int)(sizeof(V) / 4);
-  static_assert(sizeof(V) % 4 == 0, "32-bit words");
-  int w[sizeof(V) / 4];
-  __builtin_memcpy(w, &v, sizeof(V));
-#pragma unroll
-  for (int k = 0; k < N; k++) w[k] = __builtin_amdgcn_mov_dpp(w[k], CTRL, 0xf, 0xf, false);
-  V r;
-  __builtin_memcpy(&r, w, sizeof(V));
-  return r;
-}
-template <typename V>
-__device__ __forceinline__ V read_lane(V v, int l) {
-  int w[sizeof(V) / 4];
-  __builtin_memcpy(w, &v, sizeof(V));
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(V) / 4); k++) w[k] = __builtin_amdgcn_readlane(w[k], l);
-  V r;
-  __builtin_memcpy(&r, w, sizeof(V));
-  return r;
-}
-// Reduction of one value per lane over the whole wavefront (all lanes
-// active), for an order-free op: every lane of a 16-lane row first holds the
-// row's reduction (quad swaps, then the half-row and row mirrors), then the
-// four rows are combined.
-template <int OP, typename V>
-__device__ __forceinline__ V wave_reduce_free(V v) {
-  v = Op<OP, V>::apply(v, dpp_mov<0xB1>(v));   // quad_perm [1,0,3,2]
-  v = Op<OP, V>::apply(v, dpp_mov<0x4E>(v));   // quad_perm [2,3,0,1]
-  v = Op<OP, V>::apply(v, dpp_mov<0x141>(v));  // row_half_mirror
-  v = Op<OP, V>::apply(v, dpp_mov<0x140>(v));  // row_mirror
-  return Op<OP, V>::apply(Op<OP, V>::apply(read_lane(v, 0), read_lane(v, 16)),
-                          Op<OP, V>::apply(read_lane(v, 32), read_lane(v, 48)));
-}
-
-// v from the lane that the DPP control CTRL selects, in the rows ROWMASK
-// enables; a lane without a source lane, or in a disabled row, gets old.
-template <int CTRL, int ROWMASK, typename V>
-__device__ __forceinline__ V dpp_upd(V old, V v) {
-  static_assert(sizeof(V) % 4 == 0, "32-bit words");
-  int wo[sizeof(V) / 4], wv[sizeof(V) / 4];
-  __builtin_memcpy(wo, &old, sizeof(V));
-  __builtin_memcpy(wv, &v, sizeof(V));
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(V) / 4); k++) wo[k] = __builtin_amdgcn_update_dpp(wo[k], wv[k], CTRL, ROWMASK, 0xf, false);
-  V r;
-  __builtin_memcpy(&r, wo, sizeof(V));
-  return r;
-}
-// Inclusive sum over the wavefront (all lanes active), and the exclusive one
-// beside it: shifts by 1, 2, 4, 8 inside each 16-lane row, then the last lane
-// of rows 0 and 2 added to rows 1 and 3, then lane 31 added to rows 2 and 3;
-// the exclusive value is the inclusive one shifted by a lane.  The sums are
-// associated differently from a lane-order fold: exact for integers, any
-// order is allowed where this is used on floating point (atomic mode).
-template <typename T>
-__device__ __forceinline__ T wave_scan_sum(T v, T &excl) {
-  const T z = T(0);
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x111, 0xf>(z, v));  // row_shr:1
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x112, 0xf>(z, v));  // row_shr:2
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x114, 0xf>(z, v));  // row_shr:4
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x118, 0xf>(z, v));  // row_shr:8
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x142, 0xa>(z, v));  // row_bcast:15 into rows 1, 3
-  v = Op<OP_SUM, T>::apply(v, dpp_upd<0x143, 0xc>(z, v));  // row_bcast:31 into rows 2, 3
-  excl = dpp_upd<0x138, 0xf>(z, v);                        // wave_shr:1
-  return v;
-}
 
 // Lane steps of the canonical chunk tree (lane l holds the tree of its LPT
 // leaves; lanes combine at distances 1, 2, ..., 32 while the partner's block
@@ -960,40 +904,47 @@ static int allow_lds(const void *fn, size_t bytes) {
 
 int stage_class(int64_t unit_bytes) { return unit_bytes <= 8 ? 0 : (unit_bytes <= 16 ? 1 : -1); }
 
-// Move whole units between the leaf buffer and scratch (pass A / pass C).
-template <typename Word, int DIR, int P, int FIX>
-static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx) {
+// Move whole units between the leaf buffer and scratch (pass A / pass C),
+// with the hot-root phase HS when the plan has hot roots and the op takes
+// them (ha, bs: its arguments).
+template <typename Word, int DIR, int P, int FIX, typename HS>
+static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx,
+                     const HotArgs &ha, int bs) {
   const HostPlan::Stage &hs = sf->hp.sp[cls];
   const DevPlan::Stage &ds = sf->dp.sp[cls];
   const unsigned g = (unsigned)hs.tile_leaf0.size();
   const size_t tile = ((size_t)hs.ta * W * sizeof(Word) + 15) / 16 * 16;
   const size_t runs = (size_t)hs.maxrun * sizeof(int32_t) * (FIX ? 2 : 1);  // offsets (and windows)
+  // static LDS of the hot phase: a value and a count per block of 64 entries
+  const size_t hot_static =
+      HS::mode == HOT_NONE ? 0 : (size_t)(kMoveTile / 64) * (sizeof(typename HS::type) + sizeof(int32_t));
   // The run tables go to LDS beside the tile when they fit: in half of a
   // CU's LDS (less the static group counts) two blocks share the CU (the
   // 64-VGPR build), else in all of it; otherwise they are read from memory.
-  if (tile + runs <= kMoveLdsTwo) {
+  if (tile + runs + hot_static <= kMoveLdsTwo) {
     const size_t lds = tile + runs;
-    int rc = allow_lds((const void *)&k_sp_move2<Word, DIR, P, FIX>, lds);
+    int rc = allow_lds((const void *)&k_sp_move2<Word, DIR, P, FIX, HS>, lds);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_sp_move2<Word, DIR, P, FIX>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
+    hipLaunchKernelGGL((k_sp_move2<Word, DIR, P, FIX, HS>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
                        ds.pa_run0, ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
-                       (Word *)scratch, W, (int)tile, hs.maxrun, fx);
+                       (Word *)scratch, W, (int)tile, hs.maxrun, fx, ha, bs);
     return SF_OK;
   }
-  const int run_cap = tile + runs <= kMoveLdsOne ? hs.maxrun : 0;
+  const int run_cap = tile + runs + hot_static <= kMoveLdsOne ? hs.maxrun : 0;
   const size_t lds = tile + (run_cap ? runs : 0);
-  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX>, lds);
+  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX, HS>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_sp_move<Word, DIR, P, FIX>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc, ds.pa_run0,
-                     ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
-                     (Word *)scratch, W, (int)tile, run_cap, fx);
+  hipLaunchKernelGGL((k_sp_move<Word, DIR, P, FIX, HS>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
+                     ds.pa_run0, ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
+                     (Word *)scratch, W, (int)tile, run_cap, fx, ha, bs);
   return SF_OK;
 }
-template <typename Word, int DIR, int FIX = 0>
-static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx = MoveFix{}) {
+template <typename Word, int DIR, int FIX = 0, typename HS = HotNone>
+static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx = MoveFix{},
+                     const HotArgs &ha = HotArgs{}, int bs = 1) {
   static_assert(kMoveTile == 8 * kStageThreads, "positions per thread");
   if (sf->hp.sp[cls].ta > kMoveTile) return SF_ERR_ARG;
-  return sp_move_p<Word, DIR, kMoveTile / kStageThreads, FIX>(sf, cls, leaf, scratch, W, st, fx);
+  return sp_move_p<Word, DIR, kMoveTile / kStageThreads, FIX, HS>(sf, cls, leaf, scratch, W, st, fx, ha, bs);
 }
 
 static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_t ub, hipStream_t st) {
@@ -1008,6 +959,45 @@ static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_
                   : sp_move_w<uint32_t, 1>(sf, cls, leaf, scratch, (int)(ub / 4), st);
 }
 
+// The word a hot-phase move kernel moves: one element of the unit type (the
+// typed LDS view of the tile then lines up with it).
+template <typename T>
+using ElemWord = typename std::conditional<sizeof(T) == 4, uint32_t,
+                                           typename std::conditional<sizeof(T) == 8, uint2, uint4>::type>::type;
+
+// Pass A with a hot phase (HOT_TOTALS of op OP for Reduce, HOT_PREFIX for
+// FetchAndOp): cold leaves to scratch, hot roots' group totals to gsum (and
+// every hot leaf's exclusive prefix in its group to gpre).
+template <typename T, int OP, int MODE>
+static int sp_move_hot_a(sf_s *sf, int cls, const T *leaf, T *scratch, int bs, T *gsum, T *gpre, hipStream_t st) {
+  const DevPlan &d = sf->dp;
+  const HotArgs ha{d.hx_pos, d.hx_tg, d.hx_e0, d.hx_grp0, d.hx_rpos, gsum, gpre};
+  return sp_move_w<ElemWord<T>, 0, 0, HotSpec<T, OP, MODE>>(sf, cls, (void *)leaf, scratch, bs, st, MoveFix{}, ha,
+                                                            bs);
+}
+
+// Pass C of FetchAndOp with the hot phase: cold leaves' fetched values from
+// scratch (plus the spanning runs' bases when FIX), hot leaves' from their
+// group bases and prefixes.
+template <typename T, int FIX>
+static int sp_move_hot_c(sf_s *sf, int cls, T *upd, T *scratch, int bs, const T *gbase, const T *gpre, MoveFix fx,
+                         hipStream_t st) {
+  const DevPlan &d = sf->dp;
+  const HotArgs ha{d.hx_pos, d.hx_tg, d.hx_e0, d.hx_grp0, d.hx_rpos, (void *)gbase, (void *)gpre};
+  return sp_move_w<ElemWord<T>, 1, FIX, HotSpec<T, OP_SUM, HOT_APPLY>>(sf, cls, (void *)upd, scratch, bs, st, fx, ha,
+                                                                      bs);
+}
+
+// Combine the hot roots' groups (one wavefront per hot root and element).
+template <typename T, int OP, int MODE>
+static void hot_combine(sf_s *sf, const T *gsum, T *gbase, T *root, int bs, hipStream_t st) {
+  const DevPlan &d = sf->dp;
+  const int H = (int)sf->hp.hx_root.size();
+  const int64_t waves = (int64_t)H * bs;
+  hipLaunchKernelGGL((k_hot_combine<T, OP, MODE>), dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st,
+                     d.hx_root, d.hx_rfirst, H, gsum, gbase, root, bs);
+}
+
 // LDS of a pass-B block: the window's values (cap units), then the chunk
 // descriptors and one value per chunk (at most maxbig chunks per window).
 struct PassBLds {
@@ -1020,6 +1010,30 @@ static PassBLds passb_lds(const HostPlan::Stage &hs, size_t ub) {
   return {(int)cd, (int)cv, cv + (size_t)hs.maxbig * ub};
 }
 
+// Bytes of one value per hot group, and per hot leaf (0 without hot
+// roots), 256-aligned.
+static size_t hot_group_bytes(const sf_s *sf, size_t ub) {
+  const HostPlan &h = sf->hp;
+  if (!h.hot) return 0;
+  return ((size_t)h.hx_grp0.back() * ub + 255) / 256 * 256;
+}
+static size_t hot_prefix_bytes(const sf_s *sf, size_t ub) {
+  const HostPlan &h = sf->hp;
+  if (!h.hot) return 0;
+  return ((size_t)h.hx_e0.back() * ub + 255) / 256 * 256;
+}
+
+// Whether a partitioned Reduce of op OP on T takes the hot path: any op in
+// atomic mode, and in deterministic mode the ops whose result does not
+// depend on the order of combination.  MAXLOC (no native atomic for pass B)
+// and the deterministic floating-point sum (its canonical pairwise trees)
+// keep their hot roots in the windows.
+template <typename T, int OP>
+static bool reduce_takes_hot(const sf_s *sf, bool atomic) {
+  if (!sf->hp.hot || OP == OP_MAXLOC || OP == OP_REPLACE) return false;
+  return atomic || OP == OP_MAX || OP == OP_MIN || std::is_integral<T>::value;
+}
+
 // Scratch bytes the partitioned Reduce / FetchAndOp of this SF need for a
 // unit of ub bytes (0 when the SF does not take that path).
 size_t part_scratch_need(const sf_s *sf, size_t ub) {
@@ -1029,7 +1043,7 @@ size_t part_scratch_need(const sf_s *sf, size_t ub) {
   const size_t main_bytes = ((size_t)sf->nleaves * ub + 255) / 256 * 256;
   const size_t lvl = (size_t)std::max<int64_t>(h.scratch_len, 1) * ub;
   const size_t runs = ((size_t)2 * h.sp[cls].win.size() * ub + 255) / 256 * 256;
-  return main_bytes + std::max(2 * lvl, 2 * runs);
+  return main_bytes + std::max(2 * lvl, 2 * runs + 2 * hot_group_bytes(sf, ub) + hot_prefix_bytes(sf, ub));
 }
 
 template <typename T, int OP, bool ATOM>
@@ -1061,14 +1075,32 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   const DevPlan::Stage &ds = d.sp[cls];
   const size_t lvl = (size_t)std::max<int64_t>(h.scratch_len, 1) * ub;
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
+  const bool hot = reduce_takes_hot<T, OP>(sf, atomic);
   void *s = nullptr;
-  int rc = acquire_scratch(sf, main_bytes + 2 * lvl, &s);
+  int rc = acquire_scratch(sf, main_bytes + (hot ? hot_group_bytes(sf, ub) : 2 * lvl), &s);
   if (rc) return rc;
   T *scr = (T *)s;
   T *buf[2] = {(T *)((char *)s + main_bytes), (T *)((char *)s + main_bytes + lvl)};
+  const PassBLds pl = passb_lds(hs, ub);
+  if constexpr (OP != OP_MAXLOC && OP != OP_REPLACE) {
+    if (hot) {
+      // cold roots through their windows (root updates as in atomic mode:
+      // exact for the ops that take this path in deterministic mode), hot
+      // roots from their group totals
+      T *gsum = (T *)((char *)s + main_bytes);
+      rc = sp_move_hot_a<T, OP, HOT_TOTALS>(sf, cls, leaf, scr, bs, gsum, nullptr, st);
+      if (rc) return rc;
+      if (hs.wcold > 0) {
+        rc = sp_reduce_launch<T, OP, true>((unsigned)hs.wcold, pl, st, ds.win, ds.sroot, ds.wchunk, ds.lpos,
+                                           (const T *)scr, buf[0], root, bs);
+        if (rc) return rc;
+      }
+      hot_combine<T, OP, HOT_TOTALS>(sf, gsum, nullptr, root, bs, st);
+      return sp_check();
+    }
+  }
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
-  const PassBLds pl = passb_lds(hs, ub);
   const unsigned gw = (unsigned)hs.win.size();
   if constexpr (OP != OP_MAXLOC) {
     if (atomic) {
@@ -1098,41 +1130,64 @@ int launch_fop_part(sf_s *sf, T *root, const T *leaf, T *upd, int bs, bool atomi
   const int cls = stage_class((int64_t)ub);
   const HostPlan::Stage &hs = h.sp[cls];
   const DevPlan::Stage &ds = d.sp[cls];
-  const unsigned gw = (unsigned)hs.win.size();
+  const bool hot = h.hot;
+  // pass B runs over the windows of cold roots only when hot roots take their own path
+  const unsigned gw = (unsigned)(hot ? hs.wcold : (int32_t)hs.win.size());
+  const int nspan = hot ? hs.nspan_cold : (int)hs.span_root.size();
   const bool det = !atomic && std::is_integral<T>::value;  // floating point: atomic only
-  if (det && (int64_t)2 * gw * bs >= INT32_MAX) return SF_ERR_UNSUPPORTED;  // 32-bit run-base index
-  // scratch: window-major leaf units, then run totals and run bases (2 per window)
+  if (det && (int64_t)2 * hs.win.size() * bs >= INT32_MAX) return SF_ERR_UNSUPPORTED;  // 32-bit run-base index
+  // scratch: window-major leaf units, then run totals and run bases (2 per
+  // window), then the hot groups' totals and bases
   const size_t main_bytes = ((size_t)L * ub + 255) / 256 * 256;
-  const size_t runs_bytes = ((size_t)2 * gw * ub + 255) / 256 * 256;
+  const size_t runs_bytes = ((size_t)2 * hs.win.size() * ub + 255) / 256 * 256;
+  const size_t grp_bytes = hot_group_bytes(sf, ub);
+  const size_t pre_bytes = hot_prefix_bytes(sf, ub);
   void *s = nullptr;
-  int rc = acquire_scratch(sf, main_bytes + (det ? 2 * runs_bytes : 0), &s);
+  int rc = acquire_scratch(sf, main_bytes + (det ? 2 * runs_bytes : 0) + 2 * grp_bytes + pre_bytes, &s);
   if (rc) return rc;
   T *scr = (T *)s;
   T *rtot = (T *)((char *)s + main_bytes);
   T *rbase = (T *)((char *)s + main_bytes + runs_bytes);
+  T *gsum = (T *)((char *)s + main_bytes + (det ? 2 * runs_bytes : 0));
+  T *gbase = (T *)((char *)gsum + grp_bytes);
+  T *gpre = (T *)((char *)gbase + grp_bytes);
   const PassBLds pl = passb_lds(hs, ub);
-  rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
+  rc = hot ? sp_move_hot_a<T, OP_SUM, HOT_PREFIX>(sf, cls, leaf, scr, bs, gsum, gpre, st)
+           : sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   if (!det) {
-    if ((rc = allow_lds((const void *)&k_sp_fop<T, true>, pl.bytes))) return rc;
-    hipLaunchKernelGGL((k_sp_fop<T, true>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot, ds.wchunk,
-                       ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
-    rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
+    if (gw > 0) {
+      if ((rc = allow_lds((const void *)&k_sp_fop<T, true>, pl.bytes))) return rc;
+      hipLaunchKernelGGL((k_sp_fop<T, true>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
+                         ds.wchunk, ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
+    }
+    if (hot) {
+      hot_combine<T, OP_SUM, HOT_APPLY>(sf, gsum, gbase, root, bs, st);
+      rc = sp_move_hot_c<T, 0>(sf, cls, upd, scr, bs, gbase, gpre, MoveFix{}, st);
+    } else {
+      rc = sp_move(sf, cls, 1, (void *)upd, scr, (int64_t)ub, st);
+    }
     if (rc) return rc;
     return sp_check();
   }
   if constexpr (std::is_integral<T>::value) {
-    if ((rc = allow_lds((const void *)&k_sp_fop<T, false>, pl.bytes))) return rc;
-    hipLaunchKernelGGL((k_sp_fop<T, false>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
-                       ds.wchunk, ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
-    const int nspan = (int)hs.span_root.size();
+    if (gw > 0) {
+      if ((rc = allow_lds((const void *)&k_sp_fop<T, false>, pl.bytes))) return rc;
+      hipLaunchKernelGGL((k_sp_fop<T, false>), dim3(gw), dim3(kStageThreads), pl.bytes, st, ds.win, ds.sroot,
+                         ds.wchunk, ds.lpos, scr, root, rtot, bs, pl.cd_off, pl.cv_off);
+    }
     if (nspan)
       hipLaunchKernelGGL((k_sp_span_scan<T>), dim3((unsigned)((nspan * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                          st, ds.span_first, ds.span_slot, ds.span_root, nspan, (const T *)rtot, rbase, root, bs);
     // pass C with the run bases added: one word per element
-    using EW = typename std::conditional<sizeof(T) == 4, uint32_t, uint2>::type;
     const MoveFix fx{ds.pa_runw, rbase};
-    rc = sp_move_w<EW, 1, (int)sizeof(T)>(sf, cls, (void *)upd, scr, bs, st, fx);
+    if (hot) {
+      hot_combine<T, OP_SUM, HOT_APPLY>(sf, gsum, gbase, root, bs, st);
+      rc = sp_move_hot_c<T, (int)sizeof(T)>(sf, cls, upd, scr, bs, gbase, gpre, fx, st);
+    } else {
+      using EW = typename std::conditional<sizeof(T) == 4, uint32_t, uint2>::type;
+      rc = sp_move_w<EW, 1, (int)sizeof(T)>(sf, cls, (void *)upd, scr, bs, st, fx);
+    }
     if (rc) return rc;
     return sp_check();
   }

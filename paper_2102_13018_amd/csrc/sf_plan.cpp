@@ -106,24 +106,27 @@ static DevPattern to_dev(const sf_pattern &p) {
   return d;
 }
 
-// The partitioned plan of one unit-size class.  Items in sorted order -- a
-// whole root of degree <= kSmallMaxDeg, or one level-0 chunk of a larger
-// root -- are packed greedily into windows of at most `cap` sorted leaves.
-// Scratch is window-major and, inside a window, in processing order, so:
+// The partitioned plan of one unit-size class.  Items -- a whole root of
+// degree <= kSmallMaxDeg, or one level-0 chunk of a larger root -- are
+// packed greedily into windows of at most `cap` sorted leaves, cold roots
+// first (in root order), then hot roots (is_hot), so that windows
+// [0, wcold) hold no hot root.  Every sorted leaf g gets its window win_g[g]
+// and its offset loc_g[g] inside the window; a root's leaves, and a chunk's,
+// have consecutive offsets.  Scratch is window-major and, inside a window,
+// in processing order, so:
 //  * pass A, which moves the leaves of `ta` consecutive processing positions
 //    (one pass-A tile) into scratch, writes one contiguous run per window,
 //    in increasing slot order (pa_loc with run starts, pa_run);
 //  * pass B loads one window's contiguous scratch range into LDS, moving
-//    scratch slot s to LDS offset lpos[s] (its sorted position minus the
-//    window's first sorted position).
+//    scratch slot s to LDS offset lpos[s] (the leaf's offset in the window).
 static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int32_t> &perm,
-                       const std::vector<int64_t> &proc_leaf, const std::vector<int32_t> &proc_slot, int64_t L,
-                       int32_t ta, int32_t cap) {
+                       const std::vector<int64_t> &proc_leaf, const std::vector<int32_t> &proc_slot,
+                       const std::vector<uint8_t> &is_hot, int64_t L, int32_t ta, int32_t cap) {
   const int64_t T = (int64_t)hp.troot.size();
   sp = HostPlan::Stage();
   sp.ta = ta;
   sp.cap = cap;
-  std::vector<int32_t> win_g(L);  // window of the g-th sorted leaf
+  std::vector<int32_t> win_g(L), loc_g(L);  // window of the g-th sorted leaf, its offset there
   std::vector<int32_t> small, big;  // touched-root ordinals / level-0 chunk ordinals, window-major
   DevSWin cur{};
   int64_t cur_n = 0;
@@ -147,26 +150,52 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   };
   static const std::vector<DevChunk> none;
   const std::vector<DevChunk> &lv0 = hp.levels.empty() ? none : hp.levels[0].chunks;
-  int32_t chunk = 0;
-  for (int64_t t = 0; t < T; t++) {
-    const int32_t g0 = hp.toff[t], n = hp.toff[t + 1] - g0;
-    if (n <= kSmallMaxDeg) {
-      if (cur_n + n > cap) close_window();
-      int c = 0;
-      while ((1 << c) < n) c++;
-      small_in_win.push_back({c, (int32_t)t});
-      for (int32_t g = g0; g < g0 + n; g++) win_g[g] = (int32_t)sp.win.size();
-      cur_n += n;
-    } else {
-      int32_t left = n;  // this root's level-0 chunks are the next entries of lv0
-      while (left > 0) {
-        const DevChunk &ch = lv0[chunk];
-        if (cur_n + ch.n > cap) close_window();
-        big.push_back(chunk);
-        for (int32_t g = ch.src; g < ch.src + ch.n; g++) win_g[g] = (int32_t)sp.win.size();
-        cur_n += ch.n;
-        left -= ch.n;
-        chunk++;
+  // first level-0 chunk of every large root (its chunks are consecutive in lv0)
+  std::vector<int32_t> chunk_first(T, -1);
+  {
+    int32_t c = 0;
+    for (int64_t t = 0; t < T; t++) {
+      const int32_t n = hp.toff[t + 1] - hp.toff[t];
+      if (n > kSmallMaxDeg) {
+        chunk_first[t] = c;
+        c += (n + kChunk - 1) / kChunk;
+      }
+    }
+    if (c != (int32_t)lv0.size()) return SF_ERR_ARG;
+  }
+  int64_t placed_chunks = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    if (pass == 1) {
+      if (cur_n > 0) close_window();
+      sp.wcold = (int32_t)sp.win.size();
+    }
+    for (int64_t t = 0; t < T; t++) {
+      if ((int)is_hot[t] != pass) continue;
+      const int32_t g0 = hp.toff[t], n = hp.toff[t + 1] - g0;
+      if (n <= kSmallMaxDeg) {
+        if (cur_n + n > cap) close_window();
+        int c = 0;
+        while ((1 << c) < n) c++;
+        small_in_win.push_back({c, (int32_t)t});
+        for (int32_t g = g0; g < g0 + n; g++) {
+          win_g[g] = (int32_t)sp.win.size();
+          loc_g[g] = (int32_t)(cur_n + (g - g0));
+        }
+        cur_n += n;
+      } else {
+        int32_t left = n;  // this root's level-0 chunks are consecutive in lv0
+        for (int32_t chunk = chunk_first[t]; left > 0; chunk++) {
+          const DevChunk &ch = lv0[chunk];
+          if (cur_n + ch.n > cap) close_window();
+          big.push_back(chunk);
+          for (int32_t g = ch.src; g < ch.src + ch.n; g++) {
+            win_g[g] = (int32_t)sp.win.size();
+            loc_g[g] = (int32_t)(cur_n + (g - ch.src));
+          }
+          cur_n += ch.n;
+          left -= ch.n;
+          placed_chunks++;
+        }
       }
     }
   }
@@ -175,26 +204,28 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   int64_t base = 0;
   for (int64_t w = 0; w < W; w++) {
     sp.win[w].base = (int32_t)base;
-    sp.win[w].g0 = (int32_t)base;  // windows cover the sorted order in order
+    sp.win[w].g0 = -1;  // windows are not ranges of the sorted order: offsets come from loc_g
     base += sp.win[w].n;
   }
-  if (base != L || chunk != (int32_t)lv0.size() || lv0.size() != hp.fo_chunks.size()) return SF_ERR_ARG;
-  // per-window descriptors: offsets relative to the window's first sorted leaf
+  if (base != L || placed_chunks != (int64_t)lv0.size() || lv0.size() != hp.fo_chunks.size()) return SF_ERR_ARG;
+  // per-window descriptors: offsets inside the window
   const int64_t nfo = (int64_t)hp.fo_chunks.size();
   for (int64_t w = 0; w < W; w++) {
     const DevSWin &win = sp.win[w];
     for (int32_t i = win.small0; i < win.small1; i++) {
       const int32_t t = small[i];
-      const int64_t o = hp.toff[t] - win.g0, n = hp.toff[t + 1] - hp.toff[t];
-      if (o < 0 || o + n > win.n || o > 0xffff || n > kSmallMaxDeg) return SF_ERR_ARG;
+      const int64_t n = hp.toff[t + 1] - hp.toff[t];
+      const int64_t o = loc_g[hp.toff[t]];
+      if (win_g[hp.toff[t]] != w || o + n > win.n || o > 0xffff || n > kSmallMaxDeg) return SF_ERR_ARG;
       sp.sroot.push_back({hp.troot[t], (int32_t)(o | (n << 16))});
     }
     for (int32_t i = win.big0; i < win.big1; i++) {
       const int32_t k = big[i];
       const DevChunk &ch = lv0[k];
       const int32_t r = hp.fo_chunks[k].dst;
-      const int64_t o = ch.src - win.g0;
-      if (o < 0 || o + ch.n > win.n || o > 0xffff || ch.n < 1 || ch.n > kChunk || hp.fo_chunks[k].src != ch.src)
+      const int64_t o = loc_g[ch.src];
+      if (win_g[ch.src] != w || o + ch.n > win.n || o > 0xffff || ch.n < 1 || ch.n > kChunk ||
+          hp.fo_chunks[k].src != ch.src)
         return SF_ERR_ARG;
       const int32_t first = (k == 0 || hp.fo_chunks[k - 1].dst != r) ? 1 : 0;
       const int32_t last = (k + 1 == nfo || hp.fo_chunks[k + 1].dst != r) ? 1 : 0;
@@ -217,20 +248,22 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   for (int64_t g = 0; g < L; g++) {
     const DevSWin &w = sp.win[win_g[g]];
     const int64_t s = dst[proc_of_leaf[perm[g]]];
-    if (s < w.base || s >= (int64_t)w.base + w.n || g - w.g0 > 0x3fff) return SF_ERR_ARG;
-    sp.lpos[s] = (uint16_t)(g - w.g0);
+    if (s < w.base || s >= (int64_t)w.base + w.n || loc_g[g] > 0x3fff) return SF_ERR_ARG;
+    sp.lpos[s] = (uint16_t)loc_g[g];
     slot_of_g[g] = (int32_t)s;
   }
   // Runs of a large root's chunks inside a window that are not the whole root
-  // span windows.  Such a run starts at the window's first sorted position
-  // (it continues one from the previous window; "which" 0) or ends at its
-  // last (it continues into the next; which 1).  Their slots are marked
-  // (sflag: 1 | which << 1, carried into pa_loc below), and every spanning
-  // root lists its runs (2 * window + which) in window order.
+  // span windows.  Such a run starts at the window's first offset (it
+  // continues one from the previous window; "which" 0) or ends at its last
+  // (it continues into the next; which 1).  The slots of cold roots' runs are
+  // marked (sflag: 1 | which << 1, carried into pa_loc below), and every
+  // spanning root lists its runs (2 * window + which) in window order; the
+  // leaves of hot roots are marked 2 (0x4000 alone in pa_loc).
   std::vector<uint8_t> sflag(L, 0);
   sp.span_first.assign(1, 0);
   for (int64_t w = 0; w < W; w++) {
     const DevSWin &win = sp.win[w];
+    const bool hot_win = w >= sp.wcold;
     bool have0 = false;
     for (int32_t i = win.big0; i < win.big1;) {
       const DevWChunk &c0 = sp.wchunk[i];
@@ -243,10 +276,16 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
         const int32_t which = o0 == 0 ? 0 : 1;
         if ((which == 0 && have0) || (which == 1 && o1 != win.n)) return SF_ERR_ARG;
         have0 = have0 || which == 0;
-        for (int32_t o = o0; o < o1; o++) sflag[slot_of_g[win.g0 + o]] = (uint8_t)(1 | (which << 1));
+        if (!hot_win) {
+          for (int32_t q = i; q < j; q++) {
+            const DevChunk &ch = lv0[sp.wchunk[q].k];
+            for (int32_t g = ch.src; g < ch.src + ch.n; g++) sflag[slot_of_g[g]] = (uint8_t)(1 | (which << 1));
+          }
+        }
         if (sp.span_root.empty() || sp.span_root.back() != c0.root) {
           if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
           sp.span_root.push_back(c0.root);
+          if (!hot_win) sp.nspan_cold = (int32_t)sp.span_root.size();
         }
         sp.span_slot.push_back((int32_t)(2 * w + which));
       }
@@ -254,6 +293,9 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
     }
   }
   if (!sp.span_root.empty()) sp.span_first.push_back((int32_t)sp.span_slot.size());
+  if (sp.wcold < W) {
+    for (int64_t s2 = sp.win[sp.wcold].base; s2 < L; s2++) sflag[s2] = 2;
+  }
   // pass-A tiles: increasing scratch slot inside each tile
   const int64_t ntiles = (L + ta - 1) / ta;
   if (ta > 0x2000) return SF_ERR_ARG;  // tile offsets take 13 bits
@@ -310,20 +352,15 @@ static int build_stage(HostPlan &hp, HostPlan::Stage &sp, const std::vector<int3
   return SF_OK;
 }
 
-// Window and tile sizes per unit-size class (overridable for tuning sweeps).
+// Window and tile sizes per unit-size class.  Pass-A tiles of 8192 units
+// (two 64 KB tiles of units <= 8 B share a CU; at most 8192 positions:
+// 13-bit offsets in pa_loc).  Windows of 64 KB, so that two pass-B blocks
+// share a CU: 8192 units <= 8 B (4096 and 16384 measured slower on the
+// 16M-leaf Zipf SF), 4096 units of 9..16 B (MAXLOC 222 -> 207 us against
+// one 128 KB window per CU).
 static void stage_sizes(int cls, int32_t *ta, int32_t *cap) {
-  // Pass-A tiles of 8192 units (two 64 KB tiles of units <= 8 B share a CU;
-  // at most 8192 positions: 13-bit offsets in pa_loc).  Windows of 64 KB, so
-  // that two pass-B blocks share a CU: 8192 units <= 8 B (4096 and 16384
-  // measured slower on spmv_ghost), 4096 units of 9..16 B (MAXLOC 222 -> 207
-  // us against one 128 KB window per CU).
-  const int64_t ub = cls == 0 ? 8 : 16;
-  *ta = 8192;
+  *ta = kPassATile;
   *cap = cls == 0 ? 8192 : 4096;
-  if (const char *e = getenv(cls == 0 ? "SF_SP0_CAP" : "SF_SP1_CAP")) *cap = atoi(e);
-  if (const char *e = getenv(cls == 0 ? "SF_SP0_TA" : "SF_SP1_TA")) *ta = atoi(e);
-  *cap = std::max<int32_t>(kChunk, std::min<int32_t>(*cap, (int32_t)(kStageMaxLds / ub)));
-  *ta = std::max<int32_t>(256, std::min<int32_t>(*ta, std::min<int32_t>(0x2000, (int32_t)(kStageMaxLds / ub))));
 }
 
 int analyze(sf_s *sf) {
@@ -538,6 +575,86 @@ int analyze(sf_s *sf) {
   if (sf->has_dup_roots && (pmode == 1 || (pmode == 0 && L >= kPartitionPlan))) {
     std::vector<int32_t> proc_slot(L);
     for (int64_t p = 0; p < L; p++) proc_slot[p] = (int32_t)slot(proc_leaf[p]);
+    // hot roots (they need tiles in leaf order: processing order must be
+    // leaf order, as it is when segment labels do not decrease)
+    std::vector<uint8_t> is_hot(T, 0);
+    bool leaf_order = true;
+    for (int64_t p = 0; p < L && leaf_order; p++) leaf_order = proc_leaf[p] == p;
+    if (sf->opts.hot_path == 1 && leaf_order) {
+      const int64_t ntiles = (L + kPassATile - 1) / kPassATile;
+      const int64_t dmin = std::max<int64_t>(64, kHotPerTile * ntiles);
+      std::vector<int32_t> cand;  // touched-root ordinals
+      for (int64_t t = 0; t < T; t++)
+        if (hp.toff[t + 1] - hp.toff[t] >= dmin) cand.push_back((int32_t)t);
+      std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+        return hp.toff[a + 1] - hp.toff[a] > hp.toff[b + 1] - hp.toff[b];
+      });
+      if ((int64_t)cand.size() > kHotRootsMax) cand.resize(kHotRootsMax);
+      if (!cand.empty()) {
+        std::vector<int32_t> hid(R, -1);
+        for (size_t h = 0; h < cand.size(); h++) {
+          is_hot[cand[h]] = 1;
+          hp.hx_root.push_back(hp.troot[cand[h]]);
+          hid[hp.troot[cand[h]]] = (int32_t)h;
+        }
+        const int64_t H = (int64_t)cand.size();
+        // per tile, the entries grouped by hot root (h ascending), in leaf
+        // order inside a group: walk every hot root's leaves in leaf order
+        // (processing position = leaf index here)
+        std::vector<int32_t> cnt(ntiles + 1, 0);
+        for (int64_t h = 0; h < H; h++) {
+          const int32_t t = cand[h];
+          for (int32_t g = hp.toff[t]; g < hp.toff[t + 1]; g++) cnt[perm[g] / kPassATile + 1]++;
+        }
+        for (int64_t k = 0; k < ntiles; k++) cnt[k + 1] += cnt[k];
+        hp.hx_e0.assign(cnt.begin(), cnt.end());
+        hp.hx_pos.resize(cnt[ntiles]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1), last_h(ntiles, -1), ngrp(ntiles, 0);
+        for (int64_t h = 0; h < H; h++) {
+          const int32_t t = cand[h];
+          for (int32_t g = hp.toff[t]; g < hp.toff[t + 1]; g++) {
+            const int64_t k = perm[g] / kPassATile;
+            const bool head = last_h[k] != (int32_t)h;
+            if (head) {
+              last_h[k] = (int32_t)h;
+              ngrp[k]++;
+            }
+            hp.hx_pos[fill[k]++] = (uint16_t)((perm[g] - k * kPassATile) | (head ? 0x8000 : 0));
+          }
+        }
+        hp.hx_grp0.assign(ntiles + 1, 0);
+        for (int64_t k = 0; k < ntiles; k++) hp.hx_grp0[k + 1] = hp.hx_grp0[k] + ngrp[k];
+        // per tile and hot-phase thread: the groups started before its first entry
+        hp.hx_tg.assign((size_t)ntiles * kStageThreads, 0);
+        for (int64_t k = 0; k < ntiles; k++) {
+          const int32_t e0 = hp.hx_e0[k], nh = hp.hx_e0[k + 1] - e0;
+          const int32_t K = (nh + kStageThreads - 1) / kStageThreads;
+          int32_t heads = 0, e = 0;
+          for (int32_t t = 0; t < kStageThreads; t++) {
+            const int32_t b0 = std::min(t * K, nh);
+            for (; e < b0; e++) heads += (hp.hx_pos[e0 + e] >> 15) & 1;
+            hp.hx_tg[(size_t)k * kStageThreads + t] = (uint16_t)heads;
+          }
+        }
+        std::vector<int32_t> gh(hp.hx_grp0[ntiles]);  // hot root of every group
+        for (int64_t k = 0; k < ntiles; k++) {
+          int32_t g = hp.hx_grp0[k];
+          for (int32_t e = hp.hx_e0[k]; e < hp.hx_e0[k + 1]; e++)
+            if (hp.hx_pos[e] & 0x8000) gh[g++] = hid[sf->iremote[k * kPassATile + (hp.hx_pos[e] & 0x1fff)].index];
+        }
+        // groups per hot root, in tile order: root-major positions
+        hp.hx_rfirst.assign(H + 1, 0);
+        for (int32_t h : gh) hp.hx_rfirst[h + 1]++;
+        for (int64_t h = 0; h < H; h++) {
+          hp.hx_maxgrp = std::max(hp.hx_maxgrp, hp.hx_rfirst[h + 1]);
+          hp.hx_rfirst[h + 1] += hp.hx_rfirst[h];
+        }
+        hp.hx_rpos.resize(gh.size());
+        std::vector<int32_t> rfill(hp.hx_rfirst.begin(), hp.hx_rfirst.end() - 1);
+        for (size_t g = 0; g < gh.size(); g++) hp.hx_rpos[g] = rfill[gh[g]]++;
+        hp.hot = true;
+      }
+    }
     // the two unit-size classes read the shared plan and write only their
     // own stage: built side by side
     int rcs[2] = {SF_OK, SF_OK};
@@ -545,7 +662,7 @@ int analyze(sf_s *sf) {
       try {
         int32_t ta, cap;
         stage_sizes(cls, &ta, &cap);
-        rcs[cls] = build_stage(hp, hp.sp[cls], perm, proc_leaf, proc_slot, L, ta, cap);
+        rcs[cls] = build_stage(hp, hp.sp[cls], perm, proc_leaf, proc_slot, is_hot, L, ta, cap);
       } catch (const std::bad_alloc &) {
         rcs[cls] = SF_ERR_OOM;
       }
@@ -587,9 +704,7 @@ void free_device(sf_s *sf) {
 // root is worth an LDS slot when it has at least half a hit per block
 // (otherwise flushing the slot costs as many atomics as it saves).
 AtomicShape atomic_shape(const sf_s *sf, int ntiles, size_t per_root_bytes, int grid) {
-  size_t budget = kHotLdsBytes;
-  if (const char *e = getenv("SF_ATOMIC_GRID")) grid = std::max(1, atoi(e));
-  if (const char *e = getenv("SF_HOT_LDS")) budget = (size_t)std::max(0, atoi(e));
+  const size_t budget = kHotLdsBytes;
   grid = std::max(1, std::min(grid, ntiles));
   const HostPlan &h = sf->hp;
   int n = 0;
@@ -668,6 +783,14 @@ int upload(sf_s *sf) {
     add(sp.tile_leaf0.data(), sp.tile_leaf0.size() * 4, (void **)&ds.tile_leaf0);
     add(sp.pa_slot.data(), sp.pa_slot.size() * 4, (void **)&ds.pa_slot);
   }
+
+  add(hp.hx_root.data(), hp.hx_root.size() * 4, (void **)&dp.hx_root);
+  add(hp.hx_pos.data(), hp.hx_pos.size() * 2, (void **)&dp.hx_pos);
+  add(hp.hx_e0.data(), hp.hx_e0.size() * 4, (void **)&dp.hx_e0);
+  add(hp.hx_grp0.data(), hp.hx_grp0.size() * 4, (void **)&dp.hx_grp0);
+  add(hp.hx_rfirst.data(), hp.hx_rfirst.size() * 4, (void **)&dp.hx_rfirst);
+  add(hp.hx_rpos.data(), hp.hx_rpos.size() * 4, (void **)&dp.hx_rpos);
+  add(hp.hx_tg.data(), hp.hx_tg.size() * 2, (void **)&dp.hx_tg);
 
   size_t total = 0;
   for (auto &p : parts) total += (p.bytes + 255) / 256 * 256;

@@ -56,7 +56,8 @@ class SfUnit(ctypes.Structure):
 
 class SfSetupOpts(ctypes.Structure):
     _fields_ = [("reduce_mode", ctypes.c_int32), ("use_patterns", ctypes.c_int32),
-                ("analyze_only", ctypes.c_int32), ("partition", ctypes.c_int32)]
+                ("analyze_only", ctypes.c_int32), ("partition", ctypes.c_int32),
+                ("hot_path", ctypes.c_int32)]
 
 
 class SfPattern(ctypes.Structure):
@@ -78,7 +79,7 @@ class SfInfo(ctypes.Structure):
                 ("nsegments", ctypes.c_int64), ("nroots_touched", ctypes.c_int64),
                 ("max_degree", ctypes.c_int64), ("has_dup_roots", ctypes.c_int32),
                 ("reduce_mode", ctypes.c_int32), ("nhot", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("hot_roots", ctypes.c_int64)]
 
 
 class SfBatchItem(ctypes.Structure):
@@ -186,10 +187,11 @@ class StarForest:
         self.nroots = int(nroots)
         self.nleaves = n
 
-    def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False, partition="auto"):
-        part = {"auto": 0, True: 1, False: 2, "on": 1, "off": 2}[partition]
+    def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False, partition="auto",
+              hot_path="auto"):
+        onoff = {"auto": 0, True: 1, False: 2, "on": 1, "off": 2}
         o = SfSetupOpts(MODES.get(reduce_mode, reduce_mode), int(bool(use_patterns)),
-                        int(bool(analyze_only)), part)
+                        int(bool(analyze_only)), onoff[partition], onoff[hot_path])
         check(lib().sf_setup(self.h, ctypes.byref(o)), "sf_setup")
         return self
 

@@ -88,3 +88,29 @@ def check_fetch_chain(iroot, slots, root0, leaf, fetched, root_final):
     last = np.ones(ri.size, bool)
     last[:-1] = ri[:-1] != ri[1:]
     assert np.array_equal(fi[last] + vi[last], want[ri[last]]), "chain end"
+
+
+def check_fetch_chain_fp(iroot, slots, root0, leaf, fetched, root_final, rtol):
+    """Validity of an atomic floating-point FetchAndOp SUM with leaves bounded
+    away from 0 (so that rounding cannot reorder a root's fetched values):
+    per root, sorted by fetched value, f0 = root0, f[k+1] = f[k] + v[k] and
+    final = f[last] + v[last], each within rtol * (|root0| + sum |v|) of that
+    root (the atomic-sum tolerance)."""
+    iroot = np.asarray(iroot)
+    v = np.asarray(leaf, dtype=np.float64)[slots]
+    f = np.asarray(fetched, dtype=np.float64)[slots]
+    r0 = np.asarray(root0, dtype=np.float64)
+    rf = np.asarray(root_final, dtype=np.float64)
+    scale = np.abs(r0).copy()
+    np.add.at(scale, iroot, np.abs(v))
+    order = np.lexsort((f, iroot))
+    ri, fi, vi = iroot[order], f[order], v[order]
+    tol = rtol * scale[ri]
+    first = np.ones(ri.size, bool)
+    first[1:] = ri[1:] != ri[:-1]
+    assert np.all(np.abs(fi[first] - r0[ri[first]]) <= tol[first]), "chain start"
+    nxt = ~first[1:]
+    assert np.all(np.abs(fi[1:][nxt] - (fi[:-1] + vi[:-1])[nxt]) <= tol[1:][nxt]), "chain links"
+    last = np.ones(ri.size, bool)
+    last[:-1] = ri[:-1] != ri[1:]
+    assert np.all(np.abs(fi[last] + vi[last] - rf[ri[last]]) <= tol[last]), "chain end"

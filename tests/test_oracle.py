@@ -429,3 +429,46 @@ def test_fetch_and_op_float_matches_integer_chain(orc, dtype):
     want = ri.astype(dtype).copy()
     np.maximum.at(want, g.iroot, li[g.ilocal].astype(dtype))
     assert np.array_equal(r, want)
+
+
+# ------------------------------------------ OpenMP variants (CPU baseline)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.int32, np.int64])
+@pytest.mark.parametrize("with_ilocal", [False, True])
+def test_omp_variants_equal_sequential(orc, dtype, with_ilocal):
+    """The OpenMP oracle (roots split among threads, each root's leaves still
+    in leaf order) gives the sequential oracle's bits exactly."""
+    from paper_2102_13018_amd import inputs
+    g = inputs.spmv_ghost(seed=41, nroots=3000, nleaves=60001)
+    ilocal = None
+    space = g.nleaves
+    rng = np.random.default_rng(42)
+    if with_ilocal:
+        space = g.nleaves + 7000
+        ilocal = rng.permutation(space)[:g.nleaves].astype(np.int64)
+    kind = "full" if np.dtype(dtype).kind == "i" else "normal"
+    for bs in (1, 3):
+        leaf = inputs.unit_data(rng, space, bs, dtype, kind)
+        root = inputs.unit_data(rng, g.nroots, bs, dtype, kind)
+        for op in ("sum", "max", "min", "replace"):
+            a = orc.reduce(g.nroots, g.iroot, ilocal, leaf, root, op)
+            b = orc.reduce_omp(g.nroots, g.iroot, ilocal, leaf, root, op)
+            assert a.tobytes() == b.tobytes(), (op, bs)
+            a = orc.bcast(g.nroots, g.iroot, ilocal, root, leaf, op)
+            b = orc.bcast_omp(g.nroots, g.iroot, ilocal, root, leaf, op)
+            assert a.tobytes() == b.tobytes(), (op, bs)
+        upd = np.zeros_like(leaf)
+        ra, ua = orc.fetch_and_op(g.nroots, g.iroot, ilocal, root, leaf, upd)
+        rb, ub = orc.fetch_and_op_omp(g.nroots, g.iroot, ilocal, root, leaf, upd)
+        assert ra.tobytes() == rb.tobytes() and ua.tobytes() == ub.tobytes(), bs
+    assert orc.omp_threads() >= 1
+
+
+def test_omp_maxloc_equals_sequential(orc):
+    from paper_2102_13018_amd import inputs
+    g = inputs.spmv_ghost(seed=43, nroots=2000, nleaves=40001)
+    rng = np.random.default_rng(44)
+    leaf = inputs.maxloc_leaves(rng, g.nleaves, ties=True)
+    root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    a = orc.reduce(g.nroots, g.iroot, None, leaf, root, "maxloc")
+    b = orc.reduce_omp(g.nroots, g.iroot, None, leaf, root, "maxloc")
+    assert np.array_equal(a["v"].view(np.uint64), b["v"].view(np.uint64)) and np.array_equal(a["i"], b["i"])
