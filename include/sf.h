@@ -251,17 +251,19 @@ int sf_fetch_and_op_end(sf_t sf, sf_unit unit, void *rootdata, const void *leafd
 
 /* --------------------------------------------------------------- batches */
 
-typedef enum { SF_KIND_BCAST = 0, SF_KIND_REDUCE = 1 } sf_kind;
+typedef enum { SF_KIND_BCAST = 0, SF_KIND_REDUCE = 1, SF_KIND_FETCH_AND_OP = 2 } sf_kind;
 
 /* One operation of a batch: an SF (set up), a unit, a kind, an op and the
- * device buffers (roots, leaves). */
+ * device buffers (roots, leaves; FetchAndOp also leafupdate, which must not
+ * be leafdata; NULL for the other kinds). */
 typedef struct {
   sf_t sf;
   sf_unit unit;
   int32_t kind; /* sf_kind */
-  int32_t op;   /* REPLACE for Bcast; SUM for Reduce */
+  int32_t op;   /* REPLACE for Bcast; SUM for Reduce and FetchAndOp */
   void *rootdata;
   void *leafdata;
+  void *leafupdate;
 } sf_batch_item;
 
 /* Batch many independent SF operations (uneven sizes, units and kinds) so
@@ -269,8 +271,15 @@ typedef struct {
  * that small kernels cannot hide).  The work table is built once here; the
  * buffers of the items are bound to the batch (the same pointers are used by
  * every launch).  The items' SFs must stay alive while the batch exists and
- * no two items may write the same buffer.  Reduce items use atomics for
- * roots of several leaves unless their SF is in DETERMINISTIC mode. */
+ * no two items may write the same buffer; an item whose SF is set up again
+ * after this call makes every later call on the batch return
+ * SF_ERR_NOT_SETUP (create a new batch).  Reduce items use atomics for roots
+ * of several leaves unless their SF is in DETERMINISTIC mode (AUTO: roots of
+ * more than 256 leaves take atomics).  FetchAndOp items (SUM) on integer
+ * units run in leaf order -- bit-identical to sf_fetch_and_op -- unless
+ * their SF is in ATOMIC mode; floating-point units use returning atomics.
+ * Autotuning of the launch shape is sf_batch_autotune's, per batch (not an
+ * option of sf_setup). */
 int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t *out);
 
 /* Run every item of the batch in one launch on stream. */

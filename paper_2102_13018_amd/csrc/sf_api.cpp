@@ -91,6 +91,7 @@ extern "C" int sf_setup(sf_t sf, const sf_setup_opts *opts) {
   sf->opts = o;
   sf->reduce_mode = o.reduce_mode;
   sf->setup = false;
+  sf->generation++;
   sf->pending.clear();
   try {
     int rc = analyze(sf);

@@ -24,6 +24,9 @@ enum BatchWork : int32_t {
   BW_RED_ATOMIC = 3,  // Reduce SUM with atomics (or plain when no duplicate roots)
   BW_RED_DET = 4,     // Reduce SUM, deterministic, one degree class
   BW_RED_WAVE = 5,    // Reduce SUM, deterministic, one wavefront per root (degree <= kChunk)
+  BW_FOP_ATOMIC = 6,  // FetchAndOp SUM with returning atomics (plain without duplicate roots)
+  BW_FOP_DET = 7,     // FetchAndOp SUM in leaf order, one degree class, a thread per (root, element)
+  BW_FOP_WAVE = 8,    // FetchAndOp SUM in leaf order, one wavefront per root of degree > kSmallMaxDeg
 };
 
 struct BatchItemDev {
@@ -34,6 +37,7 @@ struct BatchItemDev {
   const int32_t *large;
   void *root;
   void *leaf;
+  void *upd;                 // FetchAndOp: leafupdate
   int32_t dtype, bs, words;  // words: W of the move kinds
   int32_t plain;             // reduce without duplicate roots
   int32_t nv;                // elements per vector access of the deterministic reduce
@@ -193,6 +197,140 @@ __device__ __forceinline__ void bw_det_wave(const BatchItemDev &it, const BatchT
   }
 }
 
+// FetchAndOp SUM with returning atomics: each leaf fetches the partial
+// value its root has when its add arrives (some per-root order).
+template <typename T, int LPT>
+__device__ __forceinline__ void bw_fop_atomic(const BatchItemDev &it, const BatchTile &bt) {
+  const DevSegment sg = it.segs[bt.seg];
+  const int bs = it.bs;
+  const int items = (bt.t1 - bt.t0) * bs;
+  const T *leaf = (const T *)it.leaf;
+  T *root = (T *)it.root;
+  T *upd = (T *)it.upd;
+  for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * LPT) {
+    T v[LPT];
+    int64_t rp[LPT], lp[LPT];
+#pragma unroll
+    for (int u = 0; u < LPT; u++) {
+      const int q = q0 + u * kBlock;
+      rp[u] = -1;
+      if (q < items) {
+        const int lt = fdiv(q, it.magic_bs);
+        const int c = q - lt * bs;
+        const int t = bt.t0 + lt;
+        const int32_t r = seg_root_s(sg, it.ridx, t);
+        const int32_t l = seg_leaf_s(sg, it.lidx, t);
+        lp[u] = (int64_t)l * bs + c;
+        v[u] = ld_stream(leaf + lp[u]);
+        rp[u] = (int64_t)r * bs + c;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LPT; u++) {
+      if (rp[u] < 0) continue;
+      T old;
+      if (it.plain) {
+        old = root[rp[u]];
+        root[rp[u]] = Op<OP_SUM, T>::apply(old, v[u]);
+      } else {
+        old = fetch_add_g(root + rp[u], v[u]);
+      }
+      st_stream(upd + lp[u], old);
+    }
+  }
+}
+
+// FetchAndOp SUM in leaf order for the roots of one degree class (<= 32
+// leaves): a thread per (root, element) loads the root's leaves (sorted
+// list, leaf order), then hands out the running value.
+template <typename T, int D>
+__device__ __forceinline__ void bw_fop_det_class(const BatchItemDev &it, const BatchTile &bt) {
+  const int bs = it.bs;
+  const int items = (bt.t1 - bt.t0) * bs;
+  const T *leaf = (const T *)it.leaf;
+  T *root = (T *)it.root;
+  T *upd = (T *)it.upd;
+  const int32_t *cls = it.cls[bt.cls];
+  for (int q = threadIdx.x; q < items; q += kBlock) {
+    const int kk = fdiv(q, it.magic_bs);
+    const int c = q - kk * bs;
+    const int t = cls[bt.t0 + kk];
+    const int g0 = it.toff[t];
+    const int n = it.toff[t + 1] - g0;
+    int64_t sl[D];
+    T x[D];
+#pragma unroll
+    for (int p = 0; p < D; p++)
+      if (p < n) sl[p] = (int64_t)ld_stream(it.sl + g0 + p) * bs + c;
+#pragma unroll
+    for (int p = 0; p < D; p++)
+      if (p < n) x[p] = ld_stream(leaf + sl[p]);
+    T *rp = root + (int64_t)it.troot[t] * bs + c;
+    T acc = *rp;
+#pragma unroll
+    for (int p = 0; p < D; p++)
+      if (p < n) {
+        st_stream(upd + sl[p], acc);
+        acc = Op<OP_SUM, T>::apply(acc, x[p]);
+      }
+    *rp = acc;
+  }
+}
+
+// FetchAndOp SUM in leaf order for a root of degree > kSmallMaxDeg: one
+// wavefront per root walks its sorted leaf list 64 leaves at a time, an
+// exclusive wavefront scan giving each leaf the root's value before it.
+template <typename T>
+__device__ __forceinline__ void bw_fop_wave(const BatchItemDev &it, const BatchTile &bt) {
+  const int lane = threadIdx.x & 63;
+  const int bs = it.bs;
+  const T *leaf = (const T *)it.leaf;
+  T *root = (T *)it.root;
+  T *upd = (T *)it.upd;
+  for (int k = bt.t0 + (threadIdx.x >> 6); k < bt.t1; k += kBlock / 64) {
+    const int t = it.large[k];
+    const int g0 = it.toff[t];
+    const int n = it.toff[t + 1] - g0;
+    for (int c = 0; c < bs; c++) {
+      T *rp = root + (int64_t)it.troot[t] * bs + c;
+      T acc = *rp;
+      for (int a = 0; a < n; a += 64) {
+        const bool ok = a + lane < n;
+        const int64_t l = ok ? (int64_t)ld_stream(it.sl + g0 + a + lane) * bs + c : -1;
+        const T v = ok ? ld_stream(leaf + l) : T(0);
+        T inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d *= 2) {
+          const T o = shfl_up(inc, d);
+          if (lane >= d) inc = Op<OP_SUM, T>::apply(o, inc);
+        }
+        const T ex = shfl_up(inc, 1);
+        if (ok) st_stream(upd + l, lane == 0 ? acc : Op<OP_SUM, T>::apply(acc, ex));
+        acc = Op<OP_SUM, T>::apply(acc, shfl_idx(inc, 63));
+      }
+      if (lane == 0) *rp = acc;
+    }
+  }
+}
+
+template <typename T, int LPT>
+__device__ __forceinline__ void bw_fop(const BatchItemDev &it, const BatchTile &bt) {
+  if (bt.work == BW_FOP_ATOMIC) {
+    bw_fop_atomic<T, LPT>(it, bt);
+  } else if (bt.work == BW_FOP_WAVE) {
+    bw_fop_wave<T>(it, bt);
+  } else {
+    switch (bt.cls) {
+      case 0: bw_fop_det_class<T, 1>(it, bt); break;
+      case 1: bw_fop_det_class<T, 2>(it, bt); break;
+      case 2: bw_fop_det_class<T, 4>(it, bt); break;
+      case 3: bw_fop_det_class<T, 8>(it, bt); break;
+      case 4: bw_fop_det_class<T, 16>(it, bt); break;
+      default: bw_fop_det_class<T, 32>(it, bt); break;
+    }
+  }
+}
+
 template <typename T, int LPT>
 __device__ __forceinline__ void bw_reduce(const BatchItemDev &it, const BatchTile &bt) {
   if (bt.work == BW_RED_ATOMIC) {
@@ -221,6 +359,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev *__restrict
       case BW_MOVE16: bw_move<uint4, LPT>(it, bt); break;
       case BW_MOVE8: bw_move<uint2, LPT>(it, bt); break;
       case BW_MOVE4: bw_move<uint32_t, LPT>(it, bt); break;
+      case BW_FOP_ATOMIC:
+      case BW_FOP_DET:
+      case BW_FOP_WAVE:
+        switch (it.dtype) {
+          case SF_F64: bw_fop<double, LPT>(it, bt); break;
+          case SF_F32: bw_fop<float, LPT>(it, bt); break;
+          case SF_I32: bw_fop<int32_t, LPT>(it, bt); break;
+          default: bw_fop<int64_t, LPT>(it, bt); break;
+        }
+        break;
       default:
         switch (it.dtype) {
           case SF_F64: bw_reduce<double, LPT>(it, bt); break;
@@ -238,6 +386,7 @@ using namespace sfi;
 
 struct sf_batch_s {
   std::vector<sf_batch_item> items;
+  std::vector<uint64_t> gen;  // each item's SF generation when the batch was created
   std::vector<BatchItemDev> hitems;
   std::vector<BatchTile> htiles;
   BatchItemDev *ditems = nullptr;
@@ -263,6 +412,31 @@ static int batch_build_tiles(sf_batch_s *b) {
         for (int t0 = 0; t0 < n; t0 += b->tile)
           b->htiles.push_back({(int32_t)k, work, (int32_t)s, t0, std::min(n, t0 + b->tile), 0, 0, 0});
       }
+      continue;
+    }
+    if (it.kind == SF_KIND_FETCH_AND_OP) {
+      // integer units with repeated roots: in leaf order (bit-exact) unless
+      // the SF asks for atomics; floating point: atomics
+      const bool is_int = it.unit.dtype == SF_I32 || it.unit.dtype == SF_I64;
+      if (!sf->has_dup_roots || !is_int || sf->reduce_mode == SF_REDUCE_ATOMIC) {
+        for (size_t s = 0; s < sf->hp.dsegs.size(); s++) {
+          const int n = sf->hp.dsegs[s].n;
+          for (int t0 = 0; t0 < n; t0 += b->tile)
+            b->htiles.push_back({(int32_t)k, BW_FOP_ATOMIC, (int32_t)s, t0, std::min(n, t0 + b->tile), 0, 0, 0});
+        }
+        continue;
+      }
+      for (int c = 0; c < kNumClasses; c++) {
+        const int n = (int)sf->hp.cls[c].size();
+        const int per = std::max(1, b->tile >> c);
+        for (int t0 = 0; t0 < n; t0 += per)
+          b->htiles.push_back({(int32_t)k, BW_FOP_DET, 0, t0, std::min(n, t0 + per), c, 0, 0});
+      }
+      // larger roots: a wavefront each, four per tile; a tile's weight for
+      // the ordering below is its leaves
+      const int nl = (int)sf->hp.large.size();
+      for (int t0 = 0; t0 < nl; t0 += kBlock / 64)
+        b->htiles.push_back({(int32_t)k, BW_FOP_WAVE, 0, t0, std::min(nl, t0 + kBlock / 64), 0, 0, 0});
       continue;
     }
     // duplicate roots: deterministic unless the SF asks for atomics (no
@@ -309,6 +483,18 @@ static int batch_build_tiles(sf_batch_s *b) {
   return SF_OK;
 }
 
+// A batch holds device addresses of its SFs' plans (and graph mode 1 their
+// scratch): an item whose SF was set up again (or is no longer set up) since
+// the batch was created makes every use of the batch fail instead of reading
+// freed memory.
+static int batch_check(const sf_batch_s *b) {
+  for (size_t k = 0; k < b->items.size(); k++) {
+    const sf_s *sf = b->items[k].sf;
+    if (!sf->setup || sf->generation != b->gen[k]) return SF_ERR_NOT_SETUP;
+  }
+  return SF_OK;
+}
+
 static void batch_free_graph(sf_batch_s *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -340,11 +526,13 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
       return es <= 0 || it.unit.bs < 1 ? SF_ERR_ARG : SF_ERR_UNSUPPORTED;
     }
     if ((it.kind == SF_KIND_BCAST && it.op != SF_REPLACE) || (it.kind == SF_KIND_REDUCE && it.op != SF_SUM) ||
-        (it.kind != SF_KIND_BCAST && it.kind != SF_KIND_REDUCE)) {
+        (it.kind == SF_KIND_FETCH_AND_OP && it.op != SF_SUM) ||
+        (it.kind != SF_KIND_BCAST && it.kind != SF_KIND_REDUCE && it.kind != SF_KIND_FETCH_AND_OP)) {
       delete b;
       return SF_ERR_UNSUPPORTED;
     }
-    if (sf->nleaves > 0 && (!it.rootdata || !it.leafdata)) {
+    if (sf->nleaves > 0 && (!it.rootdata || !it.leafdata ||
+                            (it.kind == SF_KIND_FETCH_AND_OP && (!it.leafupdate || it.leafupdate == it.leafdata)))) {
       delete b;
       return SF_ERR_ARG;
     }
@@ -365,11 +553,12 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
     d.large = p.large;
     d.root = it.rootdata;
     d.leaf = it.leafdata;
+    d.upd = it.kind == SF_KIND_FETCH_AND_OP ? it.leafupdate : nullptr;
     d.dtype = it.unit.dtype;
     d.bs = it.unit.bs;
     d.plain = sf->has_dup_roots ? 0 : 1;
     const int64_t ub = (int64_t)es * it.unit.bs;
-    const uintptr_t a = (uintptr_t)it.rootdata | (uintptr_t)it.leafdata;
+    const uintptr_t a = (uintptr_t)it.rootdata | (uintptr_t)it.leafdata | (uintptr_t)d.upd;
     d.words = (int32_t)(ub % 16 == 0 && a % 16 == 0 ? ub / 16 : (ub % 8 == 0 && a % 8 == 0 ? ub / 8 : ub / 4));
     d.magic_words = magic_of((uint32_t)d.words);
     d.magic_bs = magic_of((uint32_t)d.bs);
@@ -381,6 +570,7 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
       d.magic_nvg = magic_of((uint32_t)(d.bs / d.nv));
     }
     b->items.push_back(it);
+    b->gen.push_back(sf->generation);
     b->hitems.push_back(d);
   }
   if (n > 0) {
@@ -422,15 +612,19 @@ static int batch_launch_lpt(sf_batch_s *b, hipStream_t st) {
 
 extern "C" int sf_batch_launch(sf_batch_t b, hipStream_t stream) {
   if (!b) return SF_ERR_ARG;
+  if (int rc = batch_check(b)) return rc;
   return batch_launch_lpt(b, stream);
 }
 
 extern "C" int sf_batch_launch_separate(sf_batch_t b, hipStream_t stream) {
   if (!b) return SF_ERR_ARG;
+  if (int rc = batch_check(b)) return rc;
   for (const sf_batch_item &it : b->items) {
     std::lock_guard<std::mutex> g(it.sf->mu);
-    int rc = it.kind == SF_KIND_BCAST ? launch_bcast(it.sf, it.unit, it.rootdata, it.leafdata, it.op, stream)
-                                      : launch_reduce(it.sf, it.unit, it.leafdata, it.rootdata, it.op, stream);
+    int rc = it.kind == SF_KIND_BCAST    ? launch_bcast(it.sf, it.unit, it.rootdata, it.leafdata, it.op, stream)
+             : it.kind == SF_KIND_REDUCE ? launch_reduce(it.sf, it.unit, it.leafdata, it.rootdata, it.op, stream)
+                                         : launch_fetch_and_op(it.sf, it.unit, it.rootdata, it.leafdata,
+                                                               it.leafupdate, it.op, stream, true);
     if (rc) return rc;
   }
   return SF_OK;
@@ -438,15 +632,17 @@ extern "C" int sf_batch_launch_separate(sf_batch_t b, hipStream_t stream) {
 
 extern "C" int sf_batch_graph_capture(sf_batch_t b, int32_t mode, hipStream_t stream) {
   if (!b || !stream || (mode != 0 && mode != 1)) return SF_ERR_ARG;
+  if (int rc = batch_check(b)) return rc;
   batch_free_graph(b);
   if (mode == 1) {
-    // the per-item path may grow scratch memory (chunk levels, or the
-    // partitioned path of large SFs): do that before capturing
+    // the per-item path may grow scratch memory (chunk levels, FetchAndOp
+    // chunk sums, or the partitioned path of large SFs): do that before
+    // capturing
     for (const sf_batch_item &it : b->items) {
-      if (it.kind != SF_KIND_REDUCE || !it.sf->has_dup_roots) continue;
+      if (it.kind == SF_KIND_BCAST || !it.sf->has_dup_roots) continue;
       const size_t ub = (size_t)it.unit.bs * elem_size(it.unit.dtype);
-      const size_t need = std::max(2 * (size_t)std::max<int64_t>(it.sf->hp.scratch_len, 1) * ub,
-                                   part_scratch_need(it.sf, ub));
+      const size_t need = std::max({2 * (size_t)std::max<int64_t>(it.sf->hp.scratch_len, 1) * ub,
+                                    it.sf->hp.fo_chunks.size() * ub, part_scratch_need(it.sf, ub)});
       int rc = ensure_scratch(it.sf, need);
       if (rc) return rc;
     }
@@ -473,6 +669,7 @@ extern "C" int sf_batch_graph_capture(sf_batch_t b, int32_t mode, hipStream_t st
 extern "C" int sf_batch_graph_launch(sf_batch_t b, hipStream_t stream) {
   if (!b) return SF_ERR_ARG;
   if (!b->exec) return SF_ERR_NOT_SETUP;
+  if (int rc = batch_check(b)) return rc;
   hipError_t e = hipGraphLaunch(b->exec, stream);
   return e == hipSuccess ? SF_OK : set_hip_error(e);
 }
@@ -489,6 +686,7 @@ extern "C" int sf_batch_set_config(sf_batch_t b, int32_t lpt, int32_t tile) {
   if (!b) return SF_ERR_ARG;
   if (!(lpt == 1 || lpt == 2 || lpt == 4 || lpt == 8)) return SF_ERR_ARG;
   if (tile < 256 || tile > (1 << 16) || (tile & (tile - 1))) return SF_ERR_ARG;
+  if (int rc = batch_check(b)) return rc;
   b->lpt = lpt;
   b->tile = tile;
   batch_free_graph(b);
@@ -519,6 +717,7 @@ static std::string batch_key(const sf_batch_s *b) {
 
 extern "C" int sf_batch_autotune(sf_batch_t b, const char *cache_path, hipStream_t stream) {
   if (!b) return SF_ERR_ARG;
+  if (int rc = batch_check(b)) return rc;
   const std::string key = batch_key(b);
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "r")) {

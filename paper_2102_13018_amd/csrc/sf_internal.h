@@ -226,6 +226,7 @@ struct sf_s {
   std::vector<sf_node> iremote_copy;
   bool setup = false;
   bool analyzed = false;
+  uint64_t generation = 0;  // incremented by every sf_setup (device plans of earlier ones are freed)
   sf_setup_opts opts{};
   int32_t reduce_mode = SF_REDUCE_AUTO;
   // analysis results
@@ -274,8 +275,10 @@ int fixed_scratch(void **ptr, size_t *bytes);
 // kernel launchers implemented in sf_kernels.hip
 int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, hipStream_t st);
 int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, hipStream_t st);
+// fp_atomic: floating-point units take atomics even in DETERMINISTIC mode
+// (as batch items do) instead of SF_ERR_UNSUPPORTED
 int launch_fetch_and_op(sf_s *sf, sf_unit unit, void *root, const void *leaf, void *upd, int op,
-                        hipStream_t st);
+                        hipStream_t st, bool fp_atomic = false);
 int elem_size(int32_t dtype);
 // launch shape of the persistent atomic kernels: grid size and the number of
 // hot roots (a prefix of hot_roots) that a block aggregates in LDS

@@ -758,12 +758,13 @@ static int fop_det_t(sf_s *sf, T *root, const T *leaf, T *upd, int bs, hipStream
   return check_launch();
 }
 
-int launch_fetch_and_op(sf_s *sf, sf_unit unit, void *root, const void *leaf, void *upd, int op, hipStream_t st) {
+int launch_fetch_and_op(sf_s *sf, sf_unit unit, void *root, const void *leaf, void *upd, int op, hipStream_t st,
+                        bool fp_atomic) {
   if (op != SF_SUM) return SF_ERR_UNSUPPORTED;
   if (sf->nleaves == 0) return SF_OK;
   const bool is_int = unit.dtype == SF_I32 || unit.dtype == SF_I64;
   int mode = sf->reduce_mode;
-  if (mode == SF_REDUCE_AUTO) mode = is_int ? SF_REDUCE_DETERMINISTIC : SF_REDUCE_ATOMIC;
+  if (mode == SF_REDUCE_AUTO || (fp_atomic && !is_int)) mode = is_int ? SF_REDUCE_DETERMINISTIC : SF_REDUCE_ATOMIC;
   if (mode == SF_REDUCE_DETERMINISTIC && !is_int) return SF_ERR_UNSUPPORTED;
   switch (unit.dtype) {
     case SF_I32:

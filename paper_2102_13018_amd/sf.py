@@ -17,7 +17,7 @@ SF_F64, SF_F32, SF_I32, SF_I64, SF_F64_I32 = 0, 1, 2, 3, 4
 SF_REPLACE, SF_SUM, SF_MAX, SF_MIN, SF_MAXLOC = 0, 1, 2, 3, 4
 SF_REDUCE_AUTO, SF_REDUCE_ATOMIC, SF_REDUCE_DETERMINISTIC = 0, 1, 2
 SF_COPY_VALUES, SF_USE_POINTER, SF_OWN_POINTER = 0, 1, 2
-SF_KIND_BCAST, SF_KIND_REDUCE = 0, 1
+SF_KIND_BCAST, SF_KIND_REDUCE, SF_KIND_FETCH_AND_OP = 0, 1, 2
 SF_PATTERN_GENERIC, SF_PATTERN_CONTIGUOUS, SF_PATTERN_3D = 0, 1, 2
 ERRORS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_DUP_LEAF", -3: "SF_ERR_NOT_SETUP",
           -4: "SF_ERR_UNSUPPORTED", -5: "SF_ERR_HIP", -6: "SF_ERR_OOM", -7: "SF_ERR_MISMATCH",
@@ -44,6 +44,9 @@ class SfError(RuntimeError):
         if code == -5:
             msg += f" (hipError {lib().sf_last_hip_error()})"
         super().__init__(f"{where}: {msg}")
+
+    def __reduce__(self):
+        return (SfError, (self.code, str(self)))
 
 
 class SfNode(ctypes.Structure):
@@ -84,7 +87,8 @@ class SfInfo(ctypes.Structure):
 
 class SfBatchItem(ctypes.Structure):
     _fields_ = [("sf", ctypes.c_void_p), ("unit", SfUnit), ("kind", ctypes.c_int32),
-                ("op", ctypes.c_int32), ("rootdata", ctypes.c_void_p), ("leafdata", ctypes.c_void_p)]
+                ("op", ctypes.c_int32), ("rootdata", ctypes.c_void_p), ("leafdata", ctypes.c_void_p),
+                ("leafupdate", ctypes.c_void_p)]
 
 
 _lib = None
@@ -142,6 +146,29 @@ def _ptr(x):
     return x.data_ptr()
 
 
+_UNIT_TORCH = {SF_F64: "torch.float64", SF_F32: "torch.float32", SF_I32: "torch.int32", SF_I64: "torch.int64"}
+
+
+def check_buffer(x, nunits, unit, what):
+    """Raise SfError(SF_ERR_ARG) unless a tensor argument can hold ``nunits``
+    units: a contiguous device tensor of at least that many bytes whose dtype
+    is the unit's (or a byte tensor carrying raw units, e.g. MAXLOC pairs).
+    Integer addresses are passed through unchecked."""
+    if x is None or isinstance(x, int):
+        return
+    if not getattr(x, "is_cuda", False):
+        raise SfError(-1, f"{what}: not a device tensor")
+    if not x.is_contiguous():
+        raise SfError(-1, f"{what}: not contiguous")
+    need = int(nunits) * int(unit.bs) * ELEM_SIZE[int(unit.dtype)]
+    have = int(x.numel()) * int(x.element_size())
+    if have < need:
+        raise SfError(-1, f"{what}: {have} bytes, the unit needs {need}")
+    dt = str(x.dtype)
+    if dt not in ("torch.uint8", "torch.int8") and dt != _UNIT_TORCH.get(int(unit.dtype)):
+        raise SfError(-1, f"{what}: dtype {dt} does not match the unit")
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -186,6 +213,7 @@ class StarForest:
         self.h = h
         self.nroots = int(nroots)
         self.nleaves = n
+        self.leafspace = n if il is None else (int(il.max()) + 1 if n else 0)
 
     def setup(self, reduce_mode="auto", use_patterns=True, analyze_only=False, partition="auto",
               hot_path="auto"):
@@ -199,7 +227,13 @@ class StarForest:
         check(lib().sf_set_reduce_mode(self.h, MODES.get(mode, mode)), "sf_set_reduce_mode")
 
     # ------------------------------------------------------------ begin/end
+    def _check(self, unit, root, leaf, upd=None):
+        check_buffer(root, self.nroots, unit, "rootdata")
+        check_buffer(leaf, self.leafspace, unit, "leafdata")
+        check_buffer(upd, self.leafspace, unit, "leafupdate")
+
     def bcast_begin(self, unit, root, leaf, op="replace", stream=None):
+        self._check(unit, root, leaf)
         check(lib().sf_bcast_begin(self.h, unit, _ptr(root), _ptr(leaf), OPS.get(op, op), _stream(stream)),
               "sf_bcast_begin")
 
@@ -208,10 +242,12 @@ class StarForest:
               "sf_bcast_end")
 
     def reduce_begin(self, unit, leaf, root, op="sum", stream=None):
+        self._check(unit, root, leaf)
         check(lib().sf_reduce_begin(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op), _stream(stream)),
               "sf_reduce_begin")
 
     def reduce_begin_noalloc(self, unit, leaf, root, op="sum", stream=None):
+        self._check(unit, root, leaf)
         check(lib().sf_reduce_begin_noalloc(self.h, unit, _ptr(leaf), _ptr(root), OPS.get(op, op),
                                             _stream(stream)), "sf_reduce_begin_noalloc")
 
@@ -220,6 +256,7 @@ class StarForest:
               "sf_reduce_end")
 
     def fetch_and_op_begin(self, unit, root, leaf, leafupdate, op="sum", stream=None):
+        self._check(unit, root, leaf, leafupdate)
         check(lib().sf_fetch_and_op_begin(self.h, unit, _ptr(root), _ptr(leaf), _ptr(leafupdate),
                                           OPS.get(op, op), _stream(stream)), "sf_fetch_and_op_begin")
 
@@ -271,15 +308,20 @@ class StarForest:
 
 class Batch:
     """A batch of SF operations run in one persistent launch (sf_batch_*).
-    items: list of (StarForest, unit, kind, op, root_tensor, leaf_tensor)."""
+    items: list of (StarForest, unit, kind, op, root_tensor, leaf_tensor) or,
+    for kind "fetch_and_op", (..., root, leaf, leafupdate)."""
 
     def __init__(self, items):
         arr = (SfBatchItem * len(items))()
         self._keep = []
-        for k, (sf, unit, kind, op, root, leaf) in enumerate(items):
-            kind = {"bcast": SF_KIND_BCAST, "reduce": SF_KIND_REDUCE}.get(kind, kind)
-            arr[k] = SfBatchItem(sf.h.value, unit, kind, OPS.get(op, op), _ptr(root), _ptr(leaf))
-            self._keep.append((sf, root, leaf))
+        for k, item in enumerate(items):
+            sf, unit, kind, op, root, leaf = item[:6]
+            upd = item[6] if len(item) > 6 else None
+            sf._check(unit, root, leaf, upd)
+            kind = {"bcast": SF_KIND_BCAST, "reduce": SF_KIND_REDUCE,
+                    "fetch_and_op": SF_KIND_FETCH_AND_OP}.get(kind, kind)
+            arr[k] = SfBatchItem(sf.h.value, unit, kind, OPS.get(op, op), _ptr(root), _ptr(leaf), _ptr(upd))
+            self._keep.append((sf, root, leaf, upd))
         h = ctypes.c_void_p()
         check(lib().sf_batch_create(len(items), arr, ctypes.byref(h)), "sf_batch_create")
         self.h = h

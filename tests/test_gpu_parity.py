@@ -279,6 +279,19 @@ def test_unit_shapes(dtype, bs):
     assert_same(gpu_bcast(make_sf(g), root, leaf), oracle.bcast(g.nroots, g.iroot, None, root, leaf), "bcast")
     reduce_checked(g, leaf, root, "sum", "deterministic", "reduce det")
     reduce_checked(g, leaf, root, "sum", "atomic", "reduce atomic")
+    if np.dtype(dtype).kind == "i":
+        # the direct deterministic FetchAndOp with units of several elements:
+        # a 40K-leaf Zipf SF (below the partitioning threshold, and forced
+        # off) has roots of degree above 32 (chunk sums and root scans)
+        assert np.bincount(g.iroot).max() > 32
+        ri = inputs.unit_data(rng, g.nroots, bs, dtype, "full")
+        li = inputs.unit_data(rng, g.leafspace, bs, dtype, "full")
+        u0 = np.zeros_like(li)
+        wr, wu = oracle.fetch_and_op(g.nroots, g.iroot, None, ri, li, u0)
+        sf = S.StarForest(g.nroots, g.iroot, g.ilocal, g.ranks).setup(reduce_mode="deterministic", partition="off")
+        r, u = gpu_fetch(sf, ri, li, u0)
+        assert_same(r, wr, "fetch det roots")
+        assert_same(u, wu, "fetch det leafupdate")
 
 
 def test_misaligned_buffers():
@@ -343,3 +356,19 @@ def test_contiguous_segments_copy_and_ping_pong():
         assert_same(got, oracle.bcast(n, iroot, None, root, leaf), "contiguous bcast")
         back = gpu_reduce(sf, got, np.zeros_like(root), "replace")
         assert_same(back, root, "ping-pong round trip")
+
+
+@pytest.mark.parametrize("op", ["replace", "maxloc"])
+def test_bcast_pair_units(op):
+    """Bcast of MAXLOC pairs (16-byte units) on an SF with holes: value and
+    index as the oracle's, the leaves' padding and the holes untouched."""
+    g = inputs.single_sf(seed=47, nroots=3000, nleaves=20000, leafspace=24000)
+    rng = np.random.default_rng(48)
+    root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    root["i"] = rng.integers(0, 50, g.nroots)
+    leaf = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    leaf["i"] = rng.integers(0, 50, g.leafspace)
+    leaf["pad"] = 77
+    got = gpu_bcast(make_sf(g), root, leaf, op)
+    assert_same(got, oracle.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, op), f"pair bcast {op}")
+    assert (got["pad"] == 77).all()

@@ -234,3 +234,48 @@ def test_bench_traffic_bookkeeping():
         assert t == int(ops["fetch_bytes"] + ops["write_bytes"]) and t > 0
     else:
         assert t is None
+
+
+class _FakeTensor:
+    """Stands in for a torch tensor in the binding's argument checks (no GPU)."""
+
+    def __init__(self, numel, esize, dtype, cuda=True, contiguous=True):
+        self._n, self._e, self.dtype, self.is_cuda, self._c = numel, esize, dtype, cuda, contiguous
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._e
+
+    def is_contiguous(self):
+        return self._c
+
+
+def test_binding_checks_tensor_arguments():
+    """Tensor arguments are checked before any call into the library: device,
+    contiguity, size in bytes against the units the SF needs, dtype against
+    the unit (byte tensors carry raw units)."""
+    u = S.SfUnit(S.SF_F64, 2)
+    ok = _FakeTensor(100 * 2, 8, "torch.float64")
+    S.check_buffer(ok, 100, u, "x")
+    S.check_buffer(_FakeTensor(1600, 1, "torch.uint8"), 100, u, "x")     # raw bytes
+    S.check_buffer(0x1000, 100, u, "x")                                   # an address: unchecked
+    bad = [_FakeTensor(200, 8, "torch.float64", cuda=False),               # host memory
+           _FakeTensor(200, 8, "torch.float64", contiguous=False),         # strided view
+           _FakeTensor(199, 8, "torch.float64"),                           # one element short
+           _FakeTensor(1599, 1, "torch.uint8"),                            # one byte short
+           _FakeTensor(400, 4, "torch.float32")]                           # wrong dtype
+    for t in bad:
+        with pytest.raises(S.SfError) as e:
+            S.check_buffer(t, 100, u, "x")
+        assert e.value.code == -1
+    # through the StarForest calls: rejected before the library sees them
+    sf = create(3, [0, 1, 1])
+    small = _FakeTensor(2, 8, "torch.float64")
+    with pytest.raises(S.SfError) as e:
+        sf.reduce_begin(S.SfUnit(S.SF_F64, 1), small, ok, "sum", 0)   # 3 leaf slots needed
+    assert e.value.code == -1 and "leafdata" in str(e.value)
+    with pytest.raises(S.SfError) as e:
+        sf.fetch_and_op_begin(S.SfUnit(S.SF_F64, 1), ok, ok, small, "sum", 0)
+    assert e.value.code == -1 and "leafupdate" in str(e.value)

@@ -472,3 +472,35 @@ def test_omp_maxloc_equals_sequential(orc):
     a = orc.reduce(g.nroots, g.iroot, None, leaf, root, "maxloc")
     b = orc.reduce_omp(g.nroots, g.iroot, None, leaf, root, "maxloc")
     assert np.array_equal(a["v"].view(np.uint64), b["v"].view(np.uint64)) and np.array_equal(a["i"], b["i"])
+
+
+def test_bcast_pair_units(orc):
+    """Bcast of MAXLOC pairs: REPLACE copies value and index (the padding of
+    the leaf is untouched); MAXLOC keeps, per leaf, the larger value of leaf
+    and root (-0 below +0), ties going to the smaller index -- written out
+    elementwise with NumPy."""
+    from paper_2102_13018_amd import inputs
+    g = inputs.single_sf(seed=45, nroots=400, nleaves=1500, leafspace=1800)
+    rng = np.random.default_rng(46)
+    root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    root["i"] = rng.integers(0, 50, g.nroots)
+    leaf = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    leaf["i"] = rng.integers(0, 50, g.leafspace)
+    leaf["pad"] = 77
+    got = orc.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, "replace")
+    want = leaf.copy()
+    want["v"][g.ilocal] = root["v"][g.iroot]
+    want["i"][g.ilocal] = root["i"][g.iroot]
+    assert got.tobytes() == want.tobytes()
+    got = orc.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, "maxloc")
+    lv, li = leaf["v"][g.ilocal], leaf["i"][g.ilocal]
+    rv, ri = root["v"][g.iroot], root["i"][g.iroot]
+    # the value order puts -0 below +0 (a total order); equal values: smaller index
+    gt = (rv > lv) | ((rv == lv) & ~np.signbit(rv) & np.signbit(lv))
+    eq = (rv == lv) & (np.signbit(rv) == np.signbit(lv))
+    take = gt | (eq & (ri < li))
+    want = leaf.copy()
+    want["v"][g.ilocal] = np.where(take, rv, lv)
+    want["i"][g.ilocal] = np.where(take, ri, li)
+    assert np.any(take) and np.any(~take) and np.any((rv == lv) & (ri != li))
+    assert got.tobytes() == want.tobytes()
