@@ -192,11 +192,12 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
 // Index of the t-th leaf of a segment side with a pattern (Section 5.2).
 __device__ __forceinline__ int32_t pat_index(const DevPattern &p, int32_t t) {
   if (p.kind == SF_PATTERN_CONTIGUOUS) return p.start + t;
+  // divisions by dx and dy as multiplications (magic numbers from the plan)
   const uint32_t ut = (uint32_t)t;
-  const uint32_t i = ut % (uint32_t)p.dx;
-  const uint32_t q = ut / (uint32_t)p.dx;
-  const uint32_t j = q % (uint32_t)p.dy;
-  const uint32_t k = q / (uint32_t)p.dy;
+  const uint32_t q = p.mdx ? (uint32_t)__umul64hi(p.mdx, (uint64_t)ut) : ut;
+  const uint32_t i = ut - q * (uint32_t)p.dx;
+  const uint32_t k = p.mdy ? (uint32_t)__umul64hi(p.mdy, (uint64_t)q) : q;
+  const uint32_t j = q - k * (uint32_t)p.dy;
   return p.start + (int32_t)i + p.sy * (int32_t)j + p.sz * (int32_t)k;
 }
 

@@ -29,6 +29,7 @@ constexpr int kReduceGrid = 512;     // grid of the persistent atomic Reduce (me
 constexpr int kFetchGrid = 1024;     // grid of the persistent atomic FetchAndOp (measured best)
 constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
 constexpr size_t kMaxPending = 64;   // pending begin/end pairs reserved per SF
+constexpr size_t kSplitMinUnit = 8;  // the Reduce split is taken for larger units only (measured)
 // Partitioned deterministic path for large SFs (two fully coalesced passes
 // through a window-major scratch copy of the leaves):
 constexpr int kStageThreads = 1024;      // threads per block of the staged kernels
@@ -55,6 +56,7 @@ constexpr int kPassATile = 8192;     // pass-A tile (processing positions), both
 // t = i + dx*(j + dy*k).  kind: SF_PATTERN_GENERIC / CONTIGUOUS / 3D.
 struct DevPattern {
   int32_t kind, start, dx, dy, sy, sz;
+  uint64_t mdx, mdy;  // ceil(2^64 / dx), ceil(2^64 / dy) (0 for 1): t / d = mulhi64(m, t) for t < 2^32
 };
 
 struct DevSegment {
@@ -129,6 +131,16 @@ struct HostPlan {
   std::vector<int32_t> small_all; // the degree classes concatenated, class by class
   std::vector<ChunkLevel> levels; // chunk levels of the large roots
   int64_t scratch_len = 0;        // max sequence length written by a chunk level
+  // Reduce split for SFs whose repeated roots all have at most kSmallMaxDeg
+  // leaves and hold under half of the leaves: the leaves of single-leaf roots
+  // stream (index or pattern) and update their roots plainly, the repeated
+  // roots take the register trees -- in one launch
+  // (taken for units of more than kSplitMinUnit bytes: on the 256^3 halo the
+  // leaf-order root updates of 8-byte units were slower than the root-sorted
+  // trees, 10.1 vs 7.4 us, and faster for 24-byte units, 11.6 vs 12.1 us)
+  bool split = false;
+  std::vector<uint32_t> rep_bits;  // [ceil(L / 32)] bit p: processing position p has a repeated root
+  std::vector<int32_t> rep_list;   // touched-root ordinals of the repeated roots, degree class by class
   // FetchAndOp on large roots: level-0 chunks, and per large root its chunk range
   std::vector<DevChunk> fo_chunks;
   std::vector<int32_t> fo_root_first;  // [nlarge+1] first chunk of each large root
@@ -206,6 +218,8 @@ struct DevPlan {
     int32_t *pa_runw = nullptr, *span_first = nullptr, *span_slot = nullptr, *span_root = nullptr;
     uint16_t *lpos = nullptr, *pa_loc = nullptr;
   } sp[2];
+  uint32_t *rep_bits = nullptr;
+  int32_t *rep_list = nullptr;
   int32_t *hx_root = nullptr, *hx_e0 = nullptr, *hx_grp0 = nullptr, *hx_rfirst = nullptr, *hx_rpos = nullptr;
   uint16_t *hx_pos = nullptr, *hx_tg = nullptr;
 };

@@ -91,13 +91,31 @@ __global__ __launch_bounds__(kBlock) void k_reduce_plain(const DevSegment *__res
   const DevTile tl = tiles[blockIdx.x];
   const DevSegment sg = segs[tl.seg];
   const int items = (tl.t1 - tl.t0) * bs;
-  for (int q = threadIdx.x; q < items; q += kBlock) {
-    const int t = tl.t0 + q / bs;
-    const int c = q % bs;
-    const int32_t r = seg_root(sg, ridx, t);
-    const int32_t l = seg_leaf(sg, lidx, t);
-    T *p = root + (int64_t)r * bs + c;
-    st(p, Op<OP, T>::apply(ld(p), ld(leaf + (int64_t)l * bs + c)));
+  constexpr int U = 4;  // elements per thread with all their loads in flight
+  for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * U) {
+    int64_t rq[U], lq[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int q = q0 + u * kBlock;
+      rq[u] = -1;
+      if (q < items) {
+        const int lt = bs == 1 ? q : q / bs;
+        const int t = tl.t0 + lt;
+        const int c = q - lt * bs;
+        rq[u] = (int64_t)seg_root_s(sg, ridx, t) * bs + c;
+        lq[u] = (int64_t)seg_leaf_s(sg, lidx, t) * bs + c;
+      }
+    }
+    T lv[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (rq[u] >= 0) {
+        lv[u] = ld_stream(leaf + lq[u]);
+        rv[u] = ld(root + rq[u]);
+      }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (rq[u] >= 0) st(root + rq[u], Op<OP, T>::apply(rv[u], lv[u]));
   }
 }
 
@@ -259,6 +277,79 @@ __global__ __launch_bounds__(kBlock) void k_det_small_all(const int32_t *__restr
     v = small_tree_v<T, OP, NV, 32>(sl, leaf, g0, n, bs, c);
   T *rp = root + (int64_t)troot[t] * bs + c;
   vst<T, NV>(rp, vop<OP, T, NV>(vld<T, NV>(rp), v));
+}
+
+// The Reduce split (one launch): blocks [0, ntiles) stream the leaves of the
+// single-leaf roots tile by tile (index or pattern addressing; a leaf whose
+// processing position is marked in rep_bits belongs to a repeated root and
+// is skipped) and update those roots plainly; the remaining blocks give each
+// (repeated root, element) its register tree over the root's sorted leaves,
+// exactly as k_det_small_all.  The two parts write disjoint roots.
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_reduce_split(const DevSegment *__restrict__ segs,
+                                                         const DevTile *__restrict__ tiles, int ntiles,
+                                                         const int32_t *__restrict__ ridx,
+                                                         const int32_t *__restrict__ lidx,
+                                                         const uint32_t *__restrict__ rep_bits,
+                                                         const int32_t *__restrict__ rep_list, int nrep,
+                                                         const int32_t *__restrict__ troot,
+                                                         const int32_t *__restrict__ toff,
+                                                         const int32_t *__restrict__ sl, const T *__restrict__ leaf,
+                                                         T *__restrict__ root, int bs) {
+  if ((int)blockIdx.x < ntiles) {
+    const DevTile tl = tiles[blockIdx.x];
+    const DevSegment sg = segs[tl.seg];
+    const int items = (tl.t1 - tl.t0) * bs;
+    constexpr int U = 4;  // elements per thread with all their loads in flight
+    for (int q0 = threadIdx.x; q0 < items; q0 += kBlock * U) {
+      int64_t rq[U], lq[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int q = q0 + u * kBlock;
+        rq[u] = -1;
+        if (q < items) {
+          const int lt = bs == 1 ? q : q / bs;
+          const int t = tl.t0 + lt;
+          const int c = q - lt * bs;
+          const int p = sg.pbase + t;
+          if (!((rep_bits[p >> 5] >> (p & 31)) & 1u)) {
+            rq[u] = (int64_t)seg_root_s(sg, ridx, t) * bs + c;
+            lq[u] = (int64_t)seg_leaf_s(sg, lidx, t) * bs + c;
+          }
+        }
+      }
+      T lv[U], rv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (rq[u] >= 0) {
+          lv[u] = ld_stream(leaf + lq[u]);
+          rv[u] = ld(root + rq[u]);
+        }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (rq[u] >= 0) st(root + rq[u], Op<OP, T>::apply(rv[u], lv[u]));
+    }
+    return;
+  }
+  const int64_t q = (int64_t)(blockIdx.x - ntiles) * kBlock + threadIdx.x;
+  if (q >= (int64_t)nrep * bs) return;
+  const int k = (int)(q / bs), c = (int)(q - (int64_t)k * bs);
+  const int t = rep_list[k];
+  const int g0 = toff[t];
+  const int n = toff[t + 1] - g0;
+  Vec<T, 1> v;
+  if (n <= 2)
+    v = small_tree_v<T, OP, 1, 2>(sl, leaf, g0, n, bs, c);
+  else if (n <= 4)
+    v = small_tree_v<T, OP, 1, 4>(sl, leaf, g0, n, bs, c);
+  else if (n <= 8)
+    v = small_tree_v<T, OP, 1, 8>(sl, leaf, g0, n, bs, c);
+  else if (n <= 16)
+    v = small_tree_v<T, OP, 1, 16>(sl, leaf, g0, n, bs, c);
+  else
+    v = small_tree_v<T, OP, 1, 32>(sl, leaf, g0, n, bs, c);
+  T *rp = root + (int64_t)troot[t] * bs + c;
+  vst<T, 1>(rp, vop<OP, T, 1>(vld<T, 1>(rp), v));
 }
 
 // Reduce REPLACE with duplicate roots: the last leaf in leaf order wins.
@@ -569,12 +660,24 @@ int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, h
 
 // -------------------------------------------------------------- Reduce
 template <typename T, int OP>
+static int reduce_split_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
+  const DevPlan &d = sf->dp;
+  const HostPlan &h = sf->hp;
+  const int ntiles = (int)h.tiles.size(), nrep = (int)h.rep_list.size();
+  const unsigned g = (unsigned)ntiles + nblocks((int64_t)nrep * bs);
+  hipLaunchKernelGGL((k_reduce_split<T, OP>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, ntiles, d.ridx, d.lidx,
+                     d.rep_bits, d.rep_list, nrep, d.troot, d.toff, d.sl, leaf, root, bs);
+  return check_launch();
+}
+
+template <typename T, int OP>
 static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st) {
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const size_t ub = sizeof(T) * (size_t)bs;
   if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)ub) >= 0 && scratch_fits(sf, part_scratch_need(sf, ub)))
     return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
+  if (OP != OP_REPLACE && h.split && ub > kSplitMinUnit) return reduce_split_t<T, OP>(sf, leaf, root, bs, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
     if (T_)
@@ -639,6 +742,7 @@ static int reduce_atomic_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t
   const size_t ub = sizeof(T) * (size_t)bs;
   if (h.part_red_atomic && stage_class((int64_t)ub) >= 0 && scratch_fits(sf, part_scratch_need(sf, ub)))
     return launch_reduce_part<T, OP>(sf, leaf, root, bs, true, st);
+  if (h.split && ub > kSplitMinUnit) return reduce_split_t<T, OP>(sf, leaf, root, bs, st);  // no atomics at all
   const int ntiles = (int)h.tiles.size();
   const AtomicShape sh = atomic_shape(sf, ntiles, bs * sizeof(T) + 4, kReduceGrid);
   const int32_t *ri = h.hot_roots.empty() ? d.ridx : d.ridx_hot;
@@ -706,7 +810,8 @@ int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, 
       }
       if (op != SF_MAXLOC) return SF_ERR_UNSUPPORTED;
       if (!sf->has_dup_roots) return reduce_plain_t<Pair, OP_MAXLOC>(sf, l, r, unit.bs, st);
-      if (mode == SF_REDUCE_ATOMIC) return reduce_maxloc_atomic(sf, l, r, unit.bs, st);
+      if (mode == SF_REDUCE_ATOMIC && !(sf->hp.split && 16 * (size_t)unit.bs > kSplitMinUnit))
+        return reduce_maxloc_atomic(sf, l, r, unit.bs, st);
       return reduce_det_t<Pair, OP_MAXLOC>(sf, l, r, unit.bs, st);
     }
     default: return SF_ERR_UNSUPPORTED;

@@ -95,8 +95,15 @@ sf_pattern detect_pattern(const int64_t *idx, int64_t n) {
   return p;
 }
 
+// ceil(2^64 / d) for d >= 2 (0 for d <= 1): with it, t / d = the high 64
+// bits of m * t for every t < 2^32 (Lemire, Kaser and Kurz, "Faster
+// remainder by direct computation", 2019).
+static uint64_t magic_div(int32_t d) { return d <= 1 ? 0 : ~0ull / (uint64_t)d + 1; }
+
 static DevPattern to_dev(const sf_pattern &p) {
   DevPattern d{};
+  d.mdx = magic_div(p.dx);
+  d.mdy = magic_div(p.dy);
   d.kind = p.kind;
   d.start = p.start;
   d.dx = p.dx;
@@ -532,6 +539,18 @@ int analyze(sf_s *sf) {
     hp.cls[c].push_back((int32_t)t);
   }
   for (int c = 0; c < kNumClasses; c++) hp.small_all.insert(hp.small_all.end(), hp.cls[c].begin(), hp.cls[c].end());
+  // the Reduce split: repeated roots of at most kSmallMaxDeg leaves that hold
+  // under half of the leaves
+  if (sf->has_dup_roots && maxdeg <= kSmallMaxDeg) {
+    int64_t single = (int64_t)hp.cls[0].size();
+    if (2 * single >= L) {
+      hp.split = true;
+      for (int c = 1; c < kNumClasses; c++) hp.rep_list.insert(hp.rep_list.end(), hp.cls[c].begin(), hp.cls[c].end());
+      hp.rep_bits.assign((size_t)((L + 31) / 32), 0u);
+      for (int64_t p = 0; p < L; p++)
+        if (deg[sf->iremote[proc_leaf[p]].index] > 1) hp.rep_bits[(size_t)(p >> 5)] |= 1u << (p & 31);
+    }
+  }
   // chunk levels of the large roots: level 0 reads leaves through sl, level
   // k > 0 reads the chunk results of level k-1.  Chunks are aligned at
   // multiples of kChunk of the root's own list, so every chunk result is a
@@ -784,6 +803,8 @@ int upload(sf_s *sf) {
     add(sp.pa_slot.data(), sp.pa_slot.size() * 4, (void **)&ds.pa_slot);
   }
 
+  add(hp.rep_bits.data(), hp.rep_bits.size() * 4, (void **)&dp.rep_bits);
+  add(hp.rep_list.data(), hp.rep_list.size() * 4, (void **)&dp.rep_list);
   add(hp.hx_root.data(), hp.hx_root.size() * 4, (void **)&dp.hx_root);
   add(hp.hx_pos.data(), hp.hx_pos.size() * 2, (void **)&dp.hx_pos);
   add(hp.hx_e0.data(), hp.hx_e0.size() * 4, (void **)&dp.hx_e0);

@@ -143,6 +143,36 @@ def test_halo(n, bs, use_patterns):
             assert ok, worst
 
 
+@pytest.mark.parametrize("use_patterns", [True, False])
+@pytest.mark.parametrize("mode", ["deterministic", "atomic"])
+def test_halo_reduce_split_every_op(use_patterns, mode):
+    """The halo's roots are single-leaf except on the box's edges (3 or 7
+    leaves): for units of more than 8 bytes the Reduce splits into a pattern
+    (or index) stream for the single-leaf roots and register trees for the
+    others, in both modes, for every op -- the oracle's bits exactly (the
+    split has no atomics); 8-byte units keep the root-sorted trees."""
+    g = inputs.halo3d(21)
+    rng = np.random.default_rng(210)
+    sf = make_sf(g, mode, use_patterns)
+    for dtype, bs in ((np.float64, 1), (np.float32, 3), (np.int32, 2), (np.int64, 1)):
+        kind = "full" if np.dtype(dtype).kind == "i" else "normal"
+        root = inputs.unit_data(rng, g.nroots, bs, dtype, kind)
+        leaf = inputs.unit_data(rng, g.leafspace, bs, dtype, kind)
+        for op in ("sum", "max", "min"):
+            got = gpu_reduce(sf, leaf, root, op)
+            want = oracle.reduce(g.nroots, g.iroot, None, leaf, root, op)
+            if (mode == "atomic" and op == "sum" and np.dtype(dtype).kind == "f"
+                    and np.dtype(dtype).itemsize * bs <= 8):  # no split: native atomics
+                ok, worst = atomic_sum_tolerance(got, want, root, leaf, g.iroot, RTOL[np.dtype(dtype)])
+                assert ok, worst
+            else:
+                assert_same(got, want, f"halo split {op} {np.dtype(dtype)} x {bs}")
+    lp = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    rp = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    assert_same(gpu_reduce(sf, lp, rp, "maxloc"), oracle.reduce(g.nroots, g.iroot, None, lp, rp, "maxloc"),
+                "halo split maxloc")
+
+
 # ------------------------------------------------------------ Zipf graph
 @pytest.fixture(scope="module")
 def zipf():
