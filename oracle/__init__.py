@@ -61,6 +61,11 @@ def lib():
         L.orc_fetch_and_op.argtypes = [i64, i64, p, p, ci, ci, ci, p, p, p]
         for f in (L.orc_bcast, L.orc_reduce, L.orc_fetch_and_op):
             f.restype = ci
+        L.orc_multi_sf.argtypes = [i64, i64, p, p, p]
+        L.orc_gather.argtypes = [i64, p, p, ci, ci, p, p]
+        L.orc_scatter.argtypes = [i64, p, p, ci, ci, p, p]
+        for f in (L.orc_multi_sf, L.orc_gather, L.orc_scatter):
+            f.restype = ci
         L.orc_pairwise_f64.argtypes = [p, i64, ci]
         L.orc_pairwise_f64.restype = ctypes.c_double
         L.orc_pairwise_f32.argtypes = [p, i64, ci]
@@ -164,6 +169,42 @@ def fetch_and_op(nroots, iroot, ilocal, rootdata, leafdata, leafupdate, op="sum"
     if rc:
         raise ValueError("oracle rejected the arguments")
     return root, upd
+
+
+def multi_sf(nroots, iroot, ilocal):
+    """The multi-SF (Section 3.2, item 2): the new root of every leaf, as an
+    int64 array over leaf indices; there are nleaves new roots."""
+    nroots, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    m = np.zeros(iroot.size, np.int64)
+    if lib().orc_multi_sf(nroots, iroot.size, _ptr(ilocal), _ptr(iroot), _ptr(m)):
+        raise ValueError("oracle rejected the arguments")
+    return m
+
+
+def gather(nroots, iroot, ilocal, leafdata, multirootdata):
+    """Return a copy of ``multirootdata`` after SFGather(leafdata)."""
+    m = multi_sf(nroots, iroot, ilocal)
+    _, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    leaf = np.ascontiguousarray(leafdata)
+    mr = np.array(multirootdata, copy=True, order="C")
+    dt, bs = _unit(leaf)
+    assert _unit(mr) == (dt, bs) and mr.shape[0] >= iroot.size
+    if lib().orc_gather(iroot.size, _ptr(ilocal), _ptr(m), dt, bs, _ptr(leaf), _ptr(mr)):
+        raise ValueError("oracle rejected the arguments")
+    return mr
+
+
+def scatter(nroots, iroot, ilocal, multirootdata, leafdata):
+    """Return a copy of ``leafdata`` after SFScatter(multirootdata)."""
+    m = multi_sf(nroots, iroot, ilocal)
+    _, iroot, ilocal = _graph(nroots, iroot, ilocal)
+    mr = np.ascontiguousarray(multirootdata)
+    leaf = np.array(leafdata, copy=True, order="C")
+    dt, bs = _unit(leaf)
+    assert _unit(mr) == (dt, bs) and mr.shape[0] >= iroot.size
+    if lib().orc_scatter(iroot.size, _ptr(ilocal), _ptr(m), dt, bs, _ptr(mr), _ptr(leaf)):
+        raise ValueError("oracle rejected the arguments")
+    return leaf
 
 
 def pairwise(x, form=PW_TOPDOWN):

@@ -294,3 +294,53 @@ int orc_fetch_and_op(int64_t nroots, int64_t nleaves, const int64_t *ilocal, con
   }
   return 0;
 }
+
+/* ------------------------------------------------ multi-SF, Gather, Scatter */
+
+/* The multi-SF of Section 3.2, item 2, built as the paper describes: every
+ * root r is split into deg(r) new roots placed at its old offset, the
+ * exclusive prefix of the degrees (the degrees being the Reduce SUM of ones),
+ * and a fetch-and-add in leaf order with the roots starting at their offset
+ * and every leaf adding 1 hands leaf i its new root mroot[i]. */
+int orc_multi_sf(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot, int64_t *mroot) {
+  if (check_graph(nroots, nleaves, ilocal, iroot, ORC_I64, 1) || (nleaves > 0 && !mroot)) return -1;
+  int64_t *deg = (int64_t *)calloc((size_t)(nroots > 0 ? nroots : 1), sizeof(int64_t));
+  int64_t *off = (int64_t *)malloc((size_t)(nroots > 0 ? nroots : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < nleaves; i++) deg[iroot[i]] += 1;
+  int64_t acc = 0;
+  for (int64_t r = 0; r < nroots; r++) {
+    off[r] = acc;
+    acc += deg[r];
+  }
+  for (int64_t i = 0; i < nleaves; i++) {  /* fetch, then add 1 */
+    mroot[i] = off[iroot[i]];
+    off[iroot[i]] += 1;
+  }
+  free(deg);
+  free(off);
+  return 0;
+}
+
+/* SFGather: multiroot[mroot[i]] = leaf[l_i] for every leaf i (whole units). */
+int orc_gather(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int dtype, int bs,
+               const void *leafdata, void *multirootdata) {
+  if (nleaves < 0 || bs < 1 || elem_size(dtype) == 0 || (nleaves > 0 && !mroot)) return -1;
+  int64_t us = elem_size(dtype) * bs;
+  for (int64_t i = 0; i < nleaves; i++) {
+    int64_t slot = ilocal ? ilocal[i] : i;
+    memcpy((char *)multirootdata + mroot[i] * us, (const char *)leafdata + slot * us, (size_t)us);
+  }
+  return 0;
+}
+
+/* SFScatter, the reverse: leaf[l_i] = multiroot[mroot[i]]; other slots untouched. */
+int orc_scatter(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int dtype, int bs,
+                const void *multirootdata, void *leafdata) {
+  if (nleaves < 0 || bs < 1 || elem_size(dtype) == 0 || (nleaves > 0 && !mroot)) return -1;
+  int64_t us = elem_size(dtype) * bs;
+  for (int64_t i = 0; i < nleaves; i++) {
+    int64_t slot = ilocal ? ilocal[i] : i;
+    memcpy((char *)leafdata + slot * us, (const char *)multirootdata + mroot[i] * us, (size_t)us);
+  }
+  return 0;
+}

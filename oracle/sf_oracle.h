@@ -62,6 +62,18 @@ int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int
 int orc_fetch_and_op(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
                      int dtype, int bs, int op, void *rootdata, const void *leafdata, void *leafupdate);
 
+/* The multi-SF of Section 3.2, item 2: mroot[i] = the new root of leaf i,
+ * from a fetch-and-add in leaf order with roots starting at the exclusive
+ * prefix of the degrees and leaves adding 1.  There are nleaves new roots. */
+int orc_multi_sf(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot, int64_t *mroot);
+
+/* SFGather: multiroot[mroot[i]] = leaf[l_i]; SFScatter: leaf[l_i] =
+ * multiroot[mroot[i]] (whole units, any dtype; pad bytes of pairs move too). */
+int orc_gather(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int dtype, int bs,
+               const void *leafdata, void *multirootdata);
+int orc_scatter(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int dtype, int bs,
+                const void *multirootdata, void *leafdata);
+
 /* Canonical pairwise sum PW of x[0..n), n >= 1:
  *   PW(x) = x[0] if n == 1, else PW(x[0..m)) + PW(x[m..n)),
  *   m = the largest power of two strictly below n          (ORC_PW_TOPDOWN)

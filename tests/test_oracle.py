@@ -504,3 +504,39 @@ def test_bcast_pair_units(orc):
     want["i"][g.ilocal] = np.where(take, ri, li)
     assert np.any(take) and np.any(~take) and np.any((rv == lv) & (ri != li))
     assert got.tobytes() == want.tobytes()
+
+
+# ------------------------------------------------ multi-SF, Gather, Scatter
+def test_fig2_gather_scatter(orc):
+    """Fig. 2's multi-SF, Gather and Scatter against the values derived by
+    hand in the fixture (Section 3.2, item 2)."""
+    fx = load_fig2()
+    il, ir = np.array(fx["ilocal"]), np.array(fx["iroot"])
+    m = orc.multi_sf(fx["nroots"], ir, il)
+    up = np.array(fx["multi_sf_fetch_and_add"]["leafupdate_after"])
+    assert np.array_equal(m, up[il])                       # the fetch-and-add's leafupdate, per leaf
+    leaf = np.arange(fx["leafspace"], dtype=np.int64) + 1
+    got = orc.gather(fx["nroots"], ir, il, leaf, np.zeros(fx["gather"]["nmulti"], np.int64))
+    assert got.tolist() == fx["gather"]["multiroot_after"]
+    mr = 100 + np.arange(fx["gather"]["nmulti"], dtype=np.int64)
+    got = orc.scatter(fx["nroots"], ir, il, mr, np.full(fx["leafspace"], -1, np.int64))
+    assert got.tolist() == fx["scatter"]["leaf_after"]
+
+
+def test_gather_groups_each_roots_leaves_in_leaf_order(orc):
+    """Brute force: the gathered multi-roots are, root by root in root
+    order, the root's leaf values in leaf order; Scatter after Gather gives
+    the connected slots back and leaves holes untouched."""
+    from paper_2102_13018_amd import inputs
+    g = inputs.single_sf(seed=48, nroots=50, nleaves=300, leafspace=400)
+    rng = np.random.default_rng(49)
+    leaf = rng.standard_normal((g.leafspace, 2))
+    mr = orc.gather(g.nroots, g.iroot, g.ilocal, leaf, np.zeros((g.nleaves, 2)))
+    want = [leaf[g.ilocal[i]] for r in range(g.nroots) for i in range(g.nleaves) if g.iroot[i] == r]
+    assert np.array_equal(mr, np.array(want))
+    back = orc.scatter(g.nroots, g.iroot, g.ilocal, mr, np.full_like(leaf, 7.0))
+    hole = np.ones(g.leafspace, bool)
+    hole[g.ilocal] = False
+    assert np.array_equal(back[~hole], leaf[~hole]) and np.all(back[hole] == 7.0)
+    m = orc.multi_sf(g.nroots, g.iroot, g.ilocal)
+    assert np.array_equal(np.sort(m), np.arange(g.nleaves))  # a permutation of the new roots
