@@ -249,6 +249,36 @@ int sf_fetch_and_op_begin(sf_t sf, sf_unit unit, void *rootdata, const void *lea
 int sf_fetch_and_op_end(sf_t sf, sf_unit unit, void *rootdata, const void *leafdata,
                         void *leafupdate, int32_t op, hipStream_t stream);
 
+/* ----------------------------------------------- multi-SF, Gather, Scatter */
+
+/* The multi-SF of sf (PetscSFGetMultiSF, Section 3.2, item 2): every root r
+ * of sf is split into deg(r) new roots, numbered from the exclusive prefix
+ * sum of the degrees (so the new roots of r are consecutive, in the leaf
+ * order of r's leaves), and leaf i of sf (same slot, same segment label) is
+ * the only leaf of its new root.  Built on the current device the first time
+ * it is asked for -- degrees by a Reduce SUM of ones, offsets by a scan, the
+ * new roots by a FetchAndOp SUM in leaf order (roots starting at their
+ * offsets, leaves adding 1) -- and then set up like any SF; synchronous.
+ *  multi: receives a handle OWNED BY sf (do not destroy it); valid until sf
+ *         is set up again or destroyed.  It has nleaves(sf) roots.
+ * Errors: SF_ERR_NOT_SETUP, SF_ERR_ARG (another device current), SF_ERR_OOM,
+ * SF_ERR_HIP. */
+int sf_get_multi_sf(sf_t sf, sf_t *multi);
+
+/* SFGather (PetscSFGatherBegin/End, Section 3.2, item 2): every leaf's unit
+ * is copied to its new root in the multi-SF: multirootdata[m_i] =
+ * leafdata[l_i], so multirootdata holds, root by root, each root's leaf
+ * units in leaf order.  Builds the multi-SF on first use (synchronously).
+ *  leafdata: [leafspace] units; multirootdata: [nleaves] units (any unit,
+ *  whole units are copied). */
+int sf_gather_begin(sf_t sf, sf_unit unit, const void *leafdata, void *multirootdata, hipStream_t stream);
+int sf_gather_end(sf_t sf, sf_unit unit, const void *leafdata, void *multirootdata, hipStream_t stream);
+
+/* SFScatter (PetscSFScatterBegin/End): the reverse of Gather,
+ * leafdata[l_i] = multirootdata[m_i]; holes are not touched. */
+int sf_scatter_begin(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata, hipStream_t stream);
+int sf_scatter_end(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata, hipStream_t stream);
+
 /* --------------------------------------------------------------- batches */
 
 typedef enum { SF_KIND_BCAST = 0, SF_KIND_REDUCE = 1, SF_KIND_FETCH_AND_OP = 2 } sf_kind;

@@ -92,6 +92,7 @@ extern "C" int sf_setup(sf_t sf, const sf_setup_opts *opts) {
   sf->reduce_mode = o.reduce_mode;
   sf->setup = false;
   sf->generation++;
+  if (sf->multi) sf_destroy(&sf->multi);  // built from the old plan
   sf->pending.clear();
   try {
     int rc = analyze(sf);
@@ -246,6 +247,54 @@ extern "C" int sf_fetch_and_op_end(sf_t sf, sf_unit unit, void *rootdata, const 
   return end_common(sf, 2, unit, op, rootdata, leafdata, leafupdate);
 }
 
+// --------------------------------------------------- Gather / Scatter
+// On the multi-SF (built on first use by sf_get_multi_sf): Gather is a
+// Reduce REPLACE onto the new roots (one leaf each), Scatter a Bcast REPLACE.
+// The pending pair is kept on the SF itself (kinds 3 and 4).
+extern "C" int sf_gather_begin(sf_t sf, sf_unit unit, const void *leafdata, void *multirootdata,
+                               hipStream_t stream) {
+  sf_t m = nullptr;
+  int rc = sf_get_multi_sf(sf, &m);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(sf->mu);
+  rc = begin_common(sf, 3, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> gm(m->mu);
+    rc = launch_reduce(m, unit, leafdata, multirootdata, SF_REPLACE, stream);
+  }
+  if (rc) return rc;
+  push_pending(sf, 3, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+  return SF_OK;
+}
+
+extern "C" int sf_gather_end(sf_t sf, sf_unit unit, const void *leafdata, void *multirootdata, hipStream_t stream) {
+  (void)stream;
+  return end_common(sf, 3, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+}
+
+extern "C" int sf_scatter_begin(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata,
+                                hipStream_t stream) {
+  sf_t m = nullptr;
+  int rc = sf_get_multi_sf(sf, &m);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(sf->mu);
+  rc = begin_common(sf, 4, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> gm(m->mu);
+    rc = launch_bcast(m, unit, multirootdata, leafdata, SF_REPLACE, stream);
+  }
+  if (rc) return rc;
+  push_pending(sf, 4, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+  return SF_OK;
+}
+
+extern "C" int sf_scatter_end(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata, hipStream_t stream) {
+  (void)stream;
+  return end_common(sf, 4, unit, SF_REPLACE, multirootdata, leafdata, nullptr);
+}
+
 // ------------------------------------------------------------ inspection
 extern "C" int sf_get_info(sf_t sf, sf_info *info) {
   if (!sf || !info) return SF_ERR_ARG;
@@ -298,6 +347,7 @@ extern "C" const char *sf_error_string(int code) {
 extern "C" int sf_destroy(sf_t *psf) {
   if (!psf) return SF_ERR_ARG;
   if (!*psf) return SF_OK;
+  if ((*psf)->multi) sf_destroy(&(*psf)->multi);
   free_device(*psf);
   delete *psf;
   *psf = nullptr;

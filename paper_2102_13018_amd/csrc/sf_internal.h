@@ -241,6 +241,7 @@ struct sf_s {
   bool setup = false;
   bool analyzed = false;
   uint64_t generation = 0;  // incremented by every sf_setup (device plans of earlier ones are freed)
+  sf_s *multi = nullptr;    // the multi-SF (Section 3.2, item 2), built on first use; owned
   sf_setup_opts opts{};
   int32_t reduce_mode = SF_REDUCE_AUTO;
   // analysis results

@@ -30,6 +30,7 @@ ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16}
 EXPORTS = [
     "sf_create", "sf_setup", "sf_set_reduce_mode", "sf_bcast_begin", "sf_bcast_end",
     "sf_reduce_begin", "sf_reduce_end", "sf_reduce_begin_noalloc", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
+    "sf_get_multi_sf", "sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end",
     "sf_batch_create", "sf_batch_launch", "sf_batch_launch_separate", "sf_batch_graph_capture",
     "sf_batch_graph_launch", "sf_batch_autotune", "sf_batch_get_config", "sf_batch_set_config",
     "sf_batch_destroy", "sf_get_info", "sf_get_segment", "sf_error_string", "sf_last_hip_error",
@@ -110,6 +111,9 @@ def lib():
             getattr(L, name).argtypes = [p, SfUnit, p, p, i32, p]
         for name in ("sf_fetch_and_op_begin", "sf_fetch_and_op_end"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, p, i32, p]
+        L.sf_get_multi_sf.argtypes = [p, ctypes.POINTER(p)]
+        for name in ("sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end"):
+            getattr(L, name).argtypes = [p, SfUnit, p, p, p]
         L.sf_batch_create.argtypes = [i32, ctypes.POINTER(SfBatchItem), ctypes.POINTER(p)]
         L.sf_batch_launch.argtypes = [p, p]
         L.sf_batch_launch_separate.argtypes = [p, p]
@@ -283,6 +287,32 @@ class StarForest:
         self.fetch_and_op_end(unit, root, leaf, leafupdate, op, stream)
         return root, leafupdate
 
+    # ------------------------------------------ multi-SF, Gather, Scatter
+    def multi_sf(self):
+        """The multi-SF (a StarForest view of a handle this SF owns)."""
+        h = ctypes.c_void_p()
+        check(lib().sf_get_multi_sf(self.h, ctypes.byref(h)), "sf_get_multi_sf")
+        m = StarForest.__new__(StarForest)
+        m.h, m.nroots, m.nleaves, m.leafspace, m._owner = h, self.nleaves, self.nleaves, self.leafspace, self
+        return m
+
+    def gather(self, leaf, multiroot, unit=None, stream=None):
+        unit = unit or unit_of(leaf)
+        check_buffer(leaf, self.leafspace, unit, "leafdata")
+        check_buffer(multiroot, self.nleaves, unit, "multirootdata")
+        check(lib().sf_gather_begin(self.h, unit, _ptr(leaf), _ptr(multiroot), _stream(stream)), "sf_gather_begin")
+        check(lib().sf_gather_end(self.h, unit, _ptr(leaf), _ptr(multiroot), _stream(stream)), "sf_gather_end")
+        return multiroot
+
+    def scatter(self, multiroot, leaf, unit=None, stream=None):
+        unit = unit or unit_of(leaf)
+        check_buffer(leaf, self.leafspace, unit, "leafdata")
+        check_buffer(multiroot, self.nleaves, unit, "multirootdata")
+        check(lib().sf_scatter_begin(self.h, unit, _ptr(multiroot), _ptr(leaf), _stream(stream)),
+              "sf_scatter_begin")
+        check(lib().sf_scatter_end(self.h, unit, _ptr(multiroot), _ptr(leaf), _stream(stream)), "sf_scatter_end")
+        return leaf
+
     # ---------------------------------------------------------- inspection
     def info(self):
         inf = SfInfo()
@@ -296,6 +326,8 @@ class StarForest:
                 "leaf": seg.leaf.as_dict()}
 
     def destroy(self):
+        if getattr(self, "_owner", None) is not None:  # a multi-SF: its owner frees it
+            return
         if getattr(self, "h", None) and self.h.value:
             lib().sf_destroy(ctypes.byref(self.h))
 
