@@ -61,6 +61,9 @@ def lib():
         L.orc_fetch_and_op.argtypes = [i64, i64, p, p, ci, ci, ci, p, p, p]
         for f in (L.orc_bcast, L.orc_reduce, L.orc_fetch_and_op):
             f.restype = ci
+        L.orc_csr_spmv.argtypes = [i64, p, p, p, p, p, ci]
+        L.orc_csr_spmv_t.argtypes = [i64, i64, p, p, p, p, p, ci]
+        L.orc_csr_spmv.restype = L.orc_csr_spmv_t.restype = ci
         L.orc_multi_sf.argtypes = [i64, i64, p, p, p]
         L.orc_gather.argtypes = [i64, p, p, ci, ci, p, p]
         L.orc_scatter.argtypes = [i64, p, p, ci, ci, p, p]
@@ -205,6 +208,44 @@ def scatter(nroots, iroot, ilocal, multirootdata, leafdata):
     if lib().orc_scatter(iroot.size, _ptr(ilocal), _ptr(m), dt, bs, _ptr(mr), _ptr(leaf)):
         raise ValueError("oracle rejected the arguments")
     return leaf
+
+
+def csr_spmv(rowptr, colidx, values, x, y=None, transpose=False, ncols=None):
+    """y = A x (or A^T x) for A in CSR (f64), plus y when given; returns a
+    new array."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    colidx = np.ascontiguousarray(colidx, np.int32)
+    values = np.ascontiguousarray(values, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    nrows = rowptr.size - 1
+    acc = y is not None
+    if transpose:
+        ncols = int(ncols if ncols is not None else (colidx.max() + 1 if colidx.size else 0))
+        out = np.array(y, np.float64, copy=True) if acc else np.zeros(ncols)
+        rc = lib().orc_csr_spmv_t(nrows, ncols, _ptr(rowptr), _ptr(colidx), _ptr(values), _ptr(x), _ptr(out),
+                                  int(acc))
+    else:
+        out = np.array(y, np.float64, copy=True) if acc else np.zeros(nrows)
+        rc = lib().orc_csr_spmv(nrows, _ptr(rowptr), _ptr(colidx), _ptr(values), _ptr(x), _ptr(out), int(acc))
+    if rc:
+        raise ValueError("oracle rejected the arguments")
+    return out
+
+
+def spmv_split(nroots, iroot, A, B, x):
+    """Section 4.1: y = M x with M = [A B] split by columns: lvec =
+    Bcast(x) over the ghost SF (leaf j <- root iroot[j]), y = A x + B lvec.
+    A, B are (rowptr, colidx, values); returns (y, lvec)."""
+    lvec = bcast(nroots, iroot, None, np.asarray(x, np.float64), np.zeros(len(iroot)))
+    y = csr_spmv(*A, x)
+    return csr_spmv(*B, lvec, y), lvec
+
+
+def spmv_split_transpose(nroots, iroot, A, B, x):
+    """y = M^T x: y = A^T x, lvec = B^T x, then Reduce SUM (lvec -> y)."""
+    y = csr_spmv(*A, x, transpose=True, ncols=nroots)
+    lvec = csr_spmv(*B, x, transpose=True, ncols=len(iroot))
+    return reduce(nroots, iroot, None, lvec, y, "sum"), lvec
 
 
 def pairwise(x, form=PW_TOPDOWN):

@@ -344,3 +344,31 @@ int orc_scatter(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, in
   }
   return 0;
 }
+
+/* --------------------------------------------- sparse products (Section 4.1) */
+
+/* y = A x (+ y when accumulate), A in CSR: row i's entries k in
+ * [rowptr[i], rowptr[i+1]) in stored order, each a[k] * x[colidx[k]]
+ * added to a running sum that starts at 0 (then added to y[i]). */
+int orc_csr_spmv(int64_t nrows, const int64_t *rowptr, const int32_t *colidx, const double *a, const double *x,
+                 double *y, int accumulate) {
+  if (nrows < 0 || !rowptr) return -1;
+  for (int64_t i = 0; i < nrows; i++) {
+    double s = 0.0;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) s = s + a[k] * x[colidx[k]];
+    y[i] = accumulate ? y[i] + s : s;
+  }
+  return 0;
+}
+
+/* y = A^T x (+ y when accumulate): every entry a[k] of row i adds
+ * a[k] * x[i] to y[colidx[k]], rows and entries in stored order. */
+int orc_csr_spmv_t(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx, const double *a,
+                   const double *x, double *y, int accumulate) {
+  if (nrows < 0 || ncols < 0 || !rowptr) return -1;
+  if (!accumulate)
+    for (int64_t j = 0; j < ncols; j++) y[j] = 0.0;
+  for (int64_t i = 0; i < nrows; i++)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) y[colidx[k]] = y[colidx[k]] + a[k] * x[i];
+  return 0;
+}

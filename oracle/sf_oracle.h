@@ -74,6 +74,13 @@ int orc_gather(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int
 int orc_scatter(int64_t nleaves, const int64_t *ilocal, const int64_t *mroot, int dtype, int bs,
                 const void *multirootdata, void *leafdata);
 
+/* Sparse products of Section 4.1 (CSR, f64): y = A x and y = A^T x, plus y
+ * when accumulate; sums in stored order (see sf_oracle.c). */
+int orc_csr_spmv(int64_t nrows, const int64_t *rowptr, const int32_t *colidx, const double *a, const double *x,
+                 double *y, int accumulate);
+int orc_csr_spmv_t(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx, const double *a,
+                   const double *x, double *y, int accumulate);
+
 /* Canonical pairwise sum PW of x[0..n), n >= 1:
  *   PW(x) = x[0] if n == 1, else PW(x[0..m)) + PW(x[m..n)),
  *   m = the largest power of two strictly below n          (ORC_PW_TOPDOWN)

@@ -21,7 +21,10 @@ Workloads (stand-ins for the paper's uses of PetscSF):
   * :func:`batch_mix`       -- many small uneven SFs (Section 5.4 launch
                                costs);
   * :func:`knn_graph`       -- k-nearest-neighbour mesh graph (DMPlex-style
-                               ghost exchange and assembly, Section 4.2).
+                               ghost exchange and assembly, Section 4.2);
+  * :func:`split_matrix`    -- one rank's diagonal / off-diagonal CSR blocks
+                               and ghost SF of a row-distributed sparse
+                               matrix (SpMV, Section 4.1).
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -194,6 +197,35 @@ def knn_graph(seed=5, npoints=1_000_000, k=8):
 
 
 # --------------------------------------------------------------- data
+def split_matrix(seed=7, n=1_000_000, nnz_a=15, m=250_000, nnz_b=4):
+    """One rank's share of a row-distributed sparse matrix (Section 4.1,
+    Fig. 3's kind): the diagonal block A (n x n CSR: the diagonal plus
+    nnz_a - 1 random columns per row), the off-diagonal block B (n x m CSR
+    over the ghost vector lvec, nnz_b random columns per row, reduced local
+    column indices), values N(0,1), and the ghost SF: lvec entry j is a leaf
+    of root iroot[j], m distinct roots of the n (the owners' local indices of
+    the ghost columns; on one device every root is local).  A stand-in for
+    the SuiteSparse matrices the paper times, which are not used.
+    Returns a dict with n, m, A = (rowptr, colidx, values), B, iroot."""
+    rng = np.random.default_rng(seed)
+
+    def csr(nrows, ncols, per_row, diag):
+        cols = rng.integers(0, ncols, (nrows, per_row), dtype=np.int64)
+        if diag:
+            cols[:, 0] = np.arange(nrows)
+        cols.sort(axis=1)
+        rowptr = np.arange(nrows + 1, dtype=np.int64) * per_row
+        vals = rng.standard_normal(nrows * per_row)
+        return rowptr, cols.reshape(-1).astype(np.int32), vals
+
+    A = csr(n, n, nnz_a, True)
+    B = csr(n, m, nnz_b, False)
+    iroot = np.sort(rng.choice(n, m, replace=False)).astype(np.int64)
+    rng.shuffle(iroot)
+    return {"n": n, "m": m, "A": A, "B": B, "iroot": iroot,
+            "meta": {"name": f"split_matrix(n={n}, nnz_a={nnz_a}, m={m}, nnz_b={nnz_b})", "seed": seed}}
+
+
 def normal(rng, shape, dtype=np.float64):
     return rng.standard_normal(shape).astype(dtype)
 

@@ -540,3 +540,42 @@ def test_gather_groups_each_roots_leaves_in_leaf_order(orc):
     assert np.array_equal(back[~hole], leaf[~hole]) and np.all(back[hole] == 7.0)
     m = orc.multi_sf(g.nroots, g.iroot, g.ilocal)
     assert np.array_equal(np.sort(m), np.arange(g.nleaves))  # a permutation of the new roots
+
+
+# ------------------------------------------------- sparse products (Section 4.1)
+def test_csr_products_hand_example(orc):
+    """A = [[2,0,1],[0,3,0],[4,0,5]], x = [1,2,3]: A x = [5,6,19],
+    A^T x = [14,6,16] (written out by hand)."""
+    rowptr = np.array([0, 2, 3, 5])
+    colidx = np.array([0, 2, 1, 0, 2])
+    vals = np.array([2.0, 1.0, 3.0, 4.0, 5.0])
+    x = np.array([1.0, 2.0, 3.0])
+    assert orc.csr_spmv(rowptr, colidx, vals, x).tolist() == [5.0, 6.0, 19.0]
+    assert orc.csr_spmv(rowptr, colidx, vals, x, transpose=True, ncols=3).tolist() == [14.0, 6.0, 16.0]
+    assert orc.csr_spmv(rowptr, colidx, vals, x, y=np.ones(3)).tolist() == [6.0, 7.0, 20.0]
+
+
+def test_csr_products_against_scipy_and_split_against_dense(orc):
+    """The CSR products equal SciPy's (the same stored-order sums); the
+    split product y = A x + B Bcast(x) equals the dense [A | B P] x, where P
+    picks lvec's entries from x, and the transpose satisfies
+    <M x, w> = <x, M^T w> within the rounding bound."""
+    import scipy.sparse as sp
+    from paper_2102_13018_amd import inputs
+    d = inputs.split_matrix(seed=70, n=400, nnz_a=6, m=90, nnz_b=3)
+    n, m, A, B, ir = d["n"], d["m"], d["A"], d["B"], d["iroot"]
+    As = sp.csr_matrix((A[2], A[1], A[0]), shape=(n, n))
+    Bs = sp.csr_matrix((B[2], B[1], B[0]), shape=(n, m))
+    rng = np.random.default_rng(71)
+    x, w = rng.standard_normal(n), rng.standard_normal(n)
+    np.testing.assert_allclose(orc.csr_spmv(*A, x), As @ x, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(orc.csr_spmv(*B, x, transpose=True, ncols=m), Bs.T @ x, rtol=0, atol=1e-12)
+    P = np.zeros((m, n))
+    P[np.arange(m), ir] = 1.0
+    M = As.toarray() + Bs.toarray() @ P
+    y, lvec = orc.spmv_split(n, ir, A, B, x)
+    assert np.array_equal(lvec, x[ir])                     # the Bcast moves values exactly
+    np.testing.assert_allclose(y, M @ x, rtol=0, atol=1e-11)
+    yt, _ = orc.spmv_split_transpose(n, ir, A, B, w)
+    np.testing.assert_allclose(yt, M.T @ w, rtol=0, atol=1e-11)
+    assert abs(np.dot(y, w) - np.dot(x, yt)) <= 1e-10 * np.abs(M).sum()
