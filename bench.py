@@ -87,7 +87,7 @@ def parse():
     p.add_argument("--no-rows", action="store_true",
                    help="time the step only: skip cold-cache times, copy ceiling, direct atomic and small / halo / batch / "
                         "autograd rows")
-    p.add_argument("--only-row", default=None, choices=["small", "halo", "batch", "autograd"],
+    p.add_argument("--only-row", default=None, choices=["small", "halo", "batch", "autograd", "spmv"],
                    help="run one row alone (for a profiler) and print its JSON")
     p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
     p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
@@ -509,6 +509,44 @@ def knn_row(torch, S, g, steps, flush, copy_gbps):
             "cache": "cold (1 GiB write before every op)", "ops": out}
 
 
+def spmv_row(torch, S, inputs, steps):
+    """Section 4.1's SpMV on one rank's share of a split matrix (1M rows, A
+    15 entries per row, B 4 per row over a 250K-entry ghost vector): y = A x
+    + B lvec with SFBcast(x -> lvec) on a second stream overlapped with A x,
+    against the same three steps serialised on one stream; and y = M^T x."""
+    d = inputs.split_matrix(seed=7)
+    dev = torch.device("cuda")
+    sf = S.StarForest(d["n"], d["iroot"]).setup()
+    A = S.Csr(d["n"], d["n"], *d["A"])
+    B = S.Csr(d["n"], d["m"], *d["B"])
+    At, Bt = A.transpose(), B.transpose()
+    rng = np.random.default_rng(8)
+    x = torch.from_numpy(rng.standard_normal(d["n"])).to(dev)
+    lvec = torch.zeros(d["m"], dtype=torch.float64, device=dev)
+    y = torch.zeros(d["n"], dtype=torch.float64, device=dev)
+    comm = torch.cuda.Stream()
+    u = S.SfUnit(S.SF_F64, 1)
+
+    def serial():
+        sf.bcast(x, lvec, "replace", unit=u)
+        A.spmv(x, y)
+        B.spmv(lvec, y, accumulate=True)
+
+    ops = [Op("overlapped", lambda: S.spmv(sf, A, B, x, lvec, y, comm_stream=comm), 0, "sf_spmv"),
+           Op("serial", serial, 0, "bcast; A x; B lvec"),
+           Op("transpose", lambda: S.spmv_transpose(sf, At, Bt, x, lvec, y), 0, "sf_spmv_transpose"),
+           Op("bcast_alone", lambda: sf.bcast(x, lvec, "replace", unit=u), 0, "k_bcast_move")]
+    time_ops(torch, ops, steps, 3)
+    out = {o.name: round(float(np.median(o.times)) * 1e3, 1) for o in ops}
+    nnz = int(d["A"][0][-1] + d["B"][0][-1])
+    # matrix bytes (8-byte values, 4-byte columns, 8-byte row offsets) and
+    # the vectors read and written once
+    mbytes = 12 * nnz + 16 * (d["n"] + 1) + 8 * (2 * d["n"] + 2 * d["m"])
+    return {"workload": d["meta"]["name"], "us": out, "overlap_saving_us": round(out["serial"] - out["overlapped"], 1),
+            "matrix_vector_MB": round(mbytes / 1e6, 1),
+            "overlapped_GBps": round(mbytes / out["overlapped"] / 1e3, 1)}
+
+
 def partition_sweep(torch, S, inputs, steps):
     """Median device time (us) of Reduce SUM f64 and FetchAndOp SUM int64 in
     both modes, with the partitioned path off, on and automatic, on Zipf SFs
@@ -575,7 +613,8 @@ def main():
         return
 
     if args.only_row:
-        fn = {"small": small_row, "halo": halo_row, "batch": batch_row, "autograd": autograd_row}[args.only_row]
+        fn = {"small": small_row, "halo": halo_row, "batch": batch_row, "autograd": autograd_row,
+              "spmv": spmv_row}[args.only_row]
         print(json.dumps({args.only_row: fn(torch, S, inputs, args.steps)}), flush=True)
         return
 
@@ -650,7 +689,7 @@ def main():
             log(f"{o.name:28s} {med * 1e3:9.1f} us  {o.nbytes / med / 1e6:8.1f} GB/s")
         out["row_direct_atomic"] = direct_row
         del sf, ops, direct, data
-        for name, fn in (("small", small_row), ("halo", halo_row), ("batch", batch_row)):
+        for name, fn in (("small", small_row), ("halo", halo_row), ("batch", batch_row), ("spmv", spmv_row)):
             try:
                 out[f"row_{name}"] = fn(torch, S, inputs, args.steps)
             except Exception as e:  # a row that cannot run is reported, not hidden

@@ -279,6 +279,42 @@ int sf_gather_end(sf_t sf, sf_unit unit, const void *leafdata, void *multirootda
 int sf_scatter_begin(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata, hipStream_t stream);
 int sf_scatter_end(sf_t sf, sf_unit unit, const void *multirootdata, void *leafdata, hipStream_t stream);
 
+/* ------------------------------------------- sparse products (Section 4.1) */
+
+/* A row-distributed sparse matrix is split on each rank into a diagonal
+ * block A (columns of the rank's own vector entries) and an off-diagonal
+ * block B (columns of the ghost vector lvec), both in CSR with reduced local
+ * column indices; the ghost SF has the n vector entries as roots and lvec's
+ * m entries as leaves (contiguous, ilocal = NULL). */
+typedef struct sf_csr_s *sf_csr_t;
+
+/* A CSR matrix of f64 values on the current device.  rowptr: [nrows + 1],
+ * rowptr[0] = 0, non-decreasing; colidx, values: [rowptr[nrows]], colidx in
+ * [0, ncols).  Host arrays, copied (also kept on the host for
+ * sf_csr_transpose).  Errors: SF_ERR_ARG, SF_ERR_OOM, SF_ERR_HIP. */
+int sf_csr_create(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx,
+                  const double *values, sf_csr_t *out);
+/* The transpose of a (a new matrix, built on the host and uploaded). */
+int sf_csr_transpose(sf_csr_t a, sf_csr_t *out);
+/* y = A x, or y += A x when accumulate != 0 (device pointers; x: [ncols],
+ * y: [nrows]), on stream. */
+int sf_csr_spmv(sf_csr_t a, const double *x, double *y, int32_t accumulate, hipStream_t stream);
+int sf_csr_destroy(sf_csr_t *a);
+
+/* y = M x for M = [A B] (Section 4.1): SFBcast REPLACE of x to lvec on sf
+ * runs on comm_stream, overlapped with y = A x on stream; stream then waits
+ * for the Bcast (an event) and computes y += B lvec.  A: n x n with n =
+ * nroots(sf); B: n x leafspace(sf).  x: [n], lvec: [leafspace], y: [n],
+ * device f64.  Enqueues only; results are visible in stream order on stream.
+ * comm_stream must have the default priority. */
+int sf_spmv(sf_t sf, sf_csr_t A, sf_csr_t B, const double *x, double *lvec, double *y, hipStream_t stream,
+            hipStream_t comm_stream);
+/* y = M^T x: y = A^T x, lvec = B^T x, then SFReduce SUM of lvec onto y, all
+ * on stream.  At, Bt: sf_csr_transpose of A and B (At: n x n, Bt:
+ * leafspace x n). */
+int sf_spmv_transpose(sf_t sf, sf_csr_t At, sf_csr_t Bt, const double *x, double *lvec, double *y,
+                      hipStream_t stream);
+
 /* --------------------------------------------------------------- batches */
 
 typedef enum { SF_KIND_BCAST = 0, SF_KIND_REDUCE = 1, SF_KIND_FETCH_AND_OP = 2 } sf_kind;

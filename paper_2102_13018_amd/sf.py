@@ -31,6 +31,7 @@ EXPORTS = [
     "sf_create", "sf_setup", "sf_set_reduce_mode", "sf_bcast_begin", "sf_bcast_end",
     "sf_reduce_begin", "sf_reduce_end", "sf_reduce_begin_noalloc", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
     "sf_get_multi_sf", "sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end",
+    "sf_csr_create", "sf_csr_transpose", "sf_csr_spmv", "sf_csr_destroy", "sf_spmv", "sf_spmv_transpose",
     "sf_batch_create", "sf_batch_launch", "sf_batch_launch_separate", "sf_batch_graph_capture",
     "sf_batch_graph_launch", "sf_batch_autotune", "sf_batch_get_config", "sf_batch_set_config",
     "sf_batch_destroy", "sf_get_info", "sf_get_segment", "sf_error_string", "sf_last_hip_error",
@@ -114,6 +115,12 @@ def lib():
         L.sf_get_multi_sf.argtypes = [p, ctypes.POINTER(p)]
         for name in ("sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, p]
+        L.sf_csr_create.argtypes = [i64, i64, p, p, p, ctypes.POINTER(p)]
+        L.sf_csr_transpose.argtypes = [p, ctypes.POINTER(p)]
+        L.sf_csr_spmv.argtypes = [p, p, p, i32, p]
+        L.sf_csr_destroy.argtypes = [ctypes.POINTER(p)]
+        L.sf_spmv.argtypes = [p, p, p, p, p, p, p, p]
+        L.sf_spmv_transpose.argtypes = [p, p, p, p, p, p, p]
         L.sf_batch_create.argtypes = [i32, ctypes.POINTER(SfBatchItem), ctypes.POINTER(p)]
         L.sf_batch_launch.argtypes = [p, p]
         L.sf_batch_launch_separate.argtypes = [p, p]
@@ -336,6 +343,69 @@ class StarForest:
             self.destroy()
         except Exception:
             pass
+
+
+class Csr:
+    """A CSR matrix of f64 values on the device (sf_csr_*): the diagonal or
+    off-diagonal block of a row-distributed matrix (Section 4.1)."""
+
+    def __init__(self, nrows, ncols, rowptr, colidx, values, _handle=None):
+        self.nrows, self.ncols = int(nrows), int(ncols)
+        if _handle is not None:
+            self.h = _handle
+            return
+        rp = np.ascontiguousarray(rowptr, np.int64)
+        ci = np.ascontiguousarray(colidx, np.int32)
+        va = np.ascontiguousarray(values, np.float64)
+        h = ctypes.c_void_p()
+        check(lib().sf_csr_create(self.nrows, self.ncols, rp.ctypes.data_as(ctypes.c_void_p),
+                                  ci.ctypes.data_as(ctypes.c_void_p), va.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(h)), "sf_csr_create")
+        self.h = h
+
+    def transpose(self):
+        h = ctypes.c_void_p()
+        check(lib().sf_csr_transpose(self.h, ctypes.byref(h)), "sf_csr_transpose")
+        return Csr(self.ncols, self.nrows, None, None, None, _handle=h)
+
+    def spmv(self, x, y, accumulate=False, stream=None):
+        check_buffer(x, self.ncols, SfUnit(SF_F64, 1), "x")
+        check_buffer(y, self.nrows, SfUnit(SF_F64, 1), "y")
+        check(lib().sf_csr_spmv(self.h, _ptr(x), _ptr(y), int(bool(accumulate)), _stream(stream)), "sf_csr_spmv")
+        return y
+
+    def destroy(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().sf_csr_destroy(ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def spmv(sf, A, B, x, lvec, y, stream=None, comm_stream=None):
+    """y = A x + B lvec with lvec = SFBcast(x) overlapped with A x (sf_spmv):
+    the Bcast on comm_stream, the products on stream."""
+    u = SfUnit(SF_F64, 1)
+    check_buffer(x, sf.nroots, u, "x")
+    check_buffer(lvec, sf.leafspace, u, "lvec")
+    check_buffer(y, A.nrows, u, "y")
+    check(lib().sf_spmv(sf.h, A.h, B.h, _ptr(x), _ptr(lvec), _ptr(y), _stream(stream), _stream(comm_stream)),
+          "sf_spmv")
+    return y
+
+
+def spmv_transpose(sf, At, Bt, x, lvec, y, stream=None):
+    """y = A^T x + SFReduce_SUM(B^T x) (sf_spmv_transpose)."""
+    u = SfUnit(SF_F64, 1)
+    check_buffer(x, At.ncols, u, "x")
+    check_buffer(lvec, sf.leafspace, u, "lvec")
+    check_buffer(y, sf.nroots, u, "y")
+    check(lib().sf_spmv_transpose(sf.h, At.h, Bt.h, _ptr(x), _ptr(lvec), _ptr(y), _stream(stream)),
+          "sf_spmv_transpose")
+    return y
 
 
 class Batch:
