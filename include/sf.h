@@ -249,6 +249,36 @@ int sf_fetch_and_op_begin(sf_t sf, sf_unit unit, void *rootdata, const void *lea
 int sf_fetch_and_op_end(sf_t sf, sf_unit unit, void *rootdata, const void *leafdata,
                         void *leafupdate, int32_t op, hipStream_t stream);
 
+/* ------------------------------------------------- composition (Section 3.3) */
+/* New SFs from existing ones: host graph algebra on the graphs given to
+ * sf_create; the results are created with their own copies of the graph and
+ * are not set up.  Segment labels follow the leaves they come from. */
+
+/* The graph of sf: ilocal[nleaves] (the slots, also when sf was created
+ * with ilocal = NULL) and iremote[nleaves]; either may be NULL. */
+int sf_get_graph(sf_t sf, int64_t *ilocal, sf_node *iremote);
+
+/* PetscSFCreateEmbeddedRootSF: only the edges whose root is one of the n
+ * selected roots remain; indices are not remapped (same nroots, same leaf
+ * slots), so the new SF communicates on the original buffers.
+ * Errors: SF_ERR_ARG (a root out of range), SF_ERR_OOM. */
+int sf_create_embedded_root_sf(sf_t sf, int64_t n, const int64_t *selected_roots, sf_t *out);
+/* PetscSFCreateEmbeddedLeafSF: only the edges whose leaf slot is one of the
+ * n selected slots remain (a selected slot without a leaf selects nothing;
+ * a negative one is SF_ERR_ARG); no remapping. */
+int sf_create_embedded_leaf_sf(sf_t sf, int64_t n, const int64_t *selected_leaves, sf_t *out);
+
+/* PetscSFCompose: a's leaf slots are b's roots (leafspace(a) <= nroots(b)).
+ * ab has a's roots and b's leaves: b's leaf at slot l on root m becomes a
+ * leaf of root r when a has a leaf at slot m on root r (b's leaves whose
+ * root is no leaf of a are dropped), so Bcast on ab = Bcast on a, then on b. */
+int sf_compose(sf_t a, sf_t b, sf_t *ab);
+/* PetscSFComposeInverse: a's and b's leaves share one leaf space and every
+ * root of b has at most one leaf (else SF_ERR_ARG).  ab has a's roots and
+ * b's roots as its leaves: b's root m (whose leaf sits at slot l) becomes a
+ * leaf of root r when a has a leaf at slot l on root r. */
+int sf_compose_inverse(sf_t a, sf_t b, sf_t *ab);
+
 /* ----------------------------------------------- multi-SF, Gather, Scatter */
 
 /* The multi-SF of sf (PetscSFGetMultiSF, Section 3.2, item 2): every root r

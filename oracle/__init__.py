@@ -301,3 +301,48 @@ def fetch_and_op_omp(nroots, iroot, ilocal, rootdata, leafdata, leafupdate, op="
     if rc:
         raise ValueError("oracle rejected the arguments")
     return root, upd
+
+
+# ------------------------------------------------ composition (Section 3.3)
+# Graphs as (nroots, iroot, ilocal, ranks) with ilocal an int64 array of
+# slots; pure Python over the edges (small cases).
+def compose(a, b):
+    """AB = a then b: a's leaf slots are b's roots; a leaf of b on root m
+    joins a's root r when a has a leaf at slot m on root r."""
+    na, ira, ila, _ = a
+    _, irb, ilb, rkb = b
+    root_at = {int(s): int(r) for s, r in zip(ila, ira)}
+    keep = [k for k in range(len(irb)) if int(irb[k]) in root_at]
+    return (na, np.array([root_at[int(irb[k])] for k in keep], np.int64), np.array([ilb[k] for k in keep], np.int64),
+            np.array([rkb[k] for k in keep], np.int64))
+
+
+def compose_inverse(a, b):
+    """a and b share a leaf space, b's roots have at most one leaf: b's root
+    m, whose leaf sits at slot l, joins a's root r when a has a leaf at l."""
+    na, ira, ila, rka = a
+    nb, irb, ilb, _ = b
+    at = {int(s): (int(r), int(q)) for s, r, q in zip(ila, ira, rka)}
+    slot_of_root = {}
+    for s, r in zip(ilb, irb):
+        assert int(r) not in slot_of_root, "b's roots must have degree <= 1"
+        slot_of_root[int(r)] = int(s)
+    keep = [m for m in range(nb) if m in slot_of_root and slot_of_root[m] in at]
+    return (na, np.array([at[slot_of_root[m]][0] for m in keep], np.int64), np.array(keep, np.int64),
+            np.array([at[slot_of_root[m]][1] for m in keep], np.int64))
+
+
+def embedded_root(sf, roots):
+    """Only the edges whose root is selected (no renumbering)."""
+    n, ir, il, rk = sf
+    sel = set(int(r) for r in roots)
+    keep = [k for k in range(len(ir)) if int(ir[k]) in sel]
+    return n, ir[keep], il[keep], rk[keep]
+
+
+def embedded_leaf(sf, slots):
+    """Only the edges whose leaf slot is selected (no renumbering)."""
+    n, ir, il, rk = sf
+    sel = set(int(s) for s in slots)
+    keep = [k for k in range(len(ir)) if int(il[k]) in sel]
+    return n, ir[keep], il[keep], rk[keep]

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsf.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["sf_api.cpp", "sf_plan.cpp", "sf_kernels.hip", "sf_partition.hip", "sf_batch.hip", "sf_noalloc.hip", "sf_multi.hip", "sf_spmv.hip"]
+SOURCES = ["sf_api.cpp", "sf_plan.cpp", "sf_compose.cpp", "sf_kernels.hip", "sf_partition.hip", "sf_batch.hip", "sf_noalloc.hip", "sf_multi.hip", "sf_spmv.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

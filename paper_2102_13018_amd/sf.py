@@ -32,6 +32,7 @@ EXPORTS = [
     "sf_reduce_begin", "sf_reduce_end", "sf_reduce_begin_noalloc", "sf_fetch_and_op_begin", "sf_fetch_and_op_end",
     "sf_get_multi_sf", "sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end",
     "sf_csr_create", "sf_csr_transpose", "sf_csr_spmv", "sf_csr_destroy", "sf_spmv", "sf_spmv_transpose",
+    "sf_get_graph", "sf_create_embedded_root_sf", "sf_create_embedded_leaf_sf", "sf_compose", "sf_compose_inverse",
     "sf_batch_create", "sf_batch_launch", "sf_batch_launch_separate", "sf_batch_graph_capture",
     "sf_batch_graph_launch", "sf_batch_autotune", "sf_batch_get_config", "sf_batch_set_config",
     "sf_batch_destroy", "sf_get_info", "sf_get_segment", "sf_error_string", "sf_last_hip_error",
@@ -112,6 +113,11 @@ def lib():
             getattr(L, name).argtypes = [p, SfUnit, p, p, i32, p]
         for name in ("sf_fetch_and_op_begin", "sf_fetch_and_op_end"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, p, i32, p]
+        L.sf_get_graph.argtypes = [p, p, p]
+        L.sf_create_embedded_root_sf.argtypes = [p, i64, p, ctypes.POINTER(p)]
+        L.sf_create_embedded_leaf_sf.argtypes = [p, i64, p, ctypes.POINTER(p)]
+        L.sf_compose.argtypes = [p, p, ctypes.POINTER(p)]
+        L.sf_compose_inverse.argtypes = [p, p, ctypes.POINTER(p)]
         L.sf_get_multi_sf.argtypes = [p, ctypes.POINTER(p)]
         for name in ("sf_gather_begin", "sf_gather_end", "sf_scatter_begin", "sf_scatter_end"):
             getattr(L, name).argtypes = [p, SfUnit, p, p, p]
@@ -293,6 +299,49 @@ class StarForest:
         self.fetch_and_op_begin(unit, root, leaf, leafupdate, op, stream)
         self.fetch_and_op_end(unit, root, leaf, leafupdate, op, stream)
         return root, leafupdate
+
+    # -------------------------------------------------------- composition
+    @classmethod
+    def _wrap(cls, h):
+        """A StarForest around a new handle from the library (owned)."""
+        sf = cls.__new__(cls)
+        sf.h = h
+        inf = SfInfo()
+        lib().sf_get_info(h, ctypes.byref(inf))  # (not set up: sizes are still filled in)
+        sf.nroots, sf.nleaves, sf.leafspace = int(inf.nroots), int(inf.nleaves), int(inf.leafspace)
+        return sf
+
+    def graph(self):
+        """(ilocal, iroot, ranks) of the SF as given to sf_create."""
+        il = np.zeros(self.nleaves, np.int64)
+        nodes = np.zeros((self.nleaves, 2), np.int64)
+        check(lib().sf_get_graph(self.h, il.ctypes.data_as(ctypes.c_void_p), nodes.ctypes.data_as(ctypes.c_void_p)),
+              "sf_get_graph")
+        return il, nodes[:, 1].copy(), nodes[:, 0].copy()
+
+    def embedded_root_sf(self, roots):
+        r = np.ascontiguousarray(roots, np.int64)
+        h = ctypes.c_void_p()
+        check(lib().sf_create_embedded_root_sf(self.h, r.size, r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+              "sf_create_embedded_root_sf")
+        return StarForest._wrap(h)
+
+    def embedded_leaf_sf(self, leaves):
+        r = np.ascontiguousarray(leaves, np.int64)
+        h = ctypes.c_void_p()
+        check(lib().sf_create_embedded_leaf_sf(self.h, r.size, r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+              "sf_create_embedded_leaf_sf")
+        return StarForest._wrap(h)
+
+    def compose(self, b):
+        h = ctypes.c_void_p()
+        check(lib().sf_compose(self.h, b.h, ctypes.byref(h)), "sf_compose")
+        return StarForest._wrap(h)
+
+    def compose_inverse(self, b):
+        h = ctypes.c_void_p()
+        check(lib().sf_compose_inverse(self.h, b.h, ctypes.byref(h)), "sf_compose_inverse")
+        return StarForest._wrap(h)
 
     # ------------------------------------------ multi-SF, Gather, Scatter
     def multi_sf(self):

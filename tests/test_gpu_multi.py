@@ -111,3 +111,37 @@ def test_fullsize_spmv_ghost_gather_scatter():
     got = gpu_gather(sf, leaf, mr0)
     assert same_bits(got, want)
     assert same_bits(gpu_scatter(sf, want, np.zeros_like(leaf)), leaf)
+
+
+def test_composed_and_embedded_sfs_on_device():
+    """SFs made by composition and embedding (Section 3.3) run like any
+    other: Bcast on A.B equals the oracle's Bcast on A then on B; Reduce on
+    an embedded root SF updates exactly the selected roots."""
+    rng = np.random.default_rng(67)
+    A = S.StarForest(3000, rng.integers(0, 3000, 9000), rng.permutation(12000)[:9000])
+    B = S.StarForest(12000, rng.integers(0, 12000, 30000), rng.permutation(40000)[:30000])
+    AB = A.compose(B).setup()
+    x = rng.standard_normal(3000)
+    ila, ira, _ = A.graph()
+    ilb, irb, _ = B.graph()
+    mid = oracle.bcast(3000, ira, ila, x, np.full(12000, -7.0))
+    two = oracle.bcast(12000, irb, ilb, mid, np.full(40000, -9.0))
+    il, _, _ = AB.graph()
+    got = np.full(40000, -9.0)
+    got = gpu_bcast_any(AB, x, got)
+    assert same_bits(got[il], two[il])
+    E = A.embedded_root_sf(np.arange(0, 3000, 3)).setup(reduce_mode="deterministic")
+    ile, ire, _ = E.graph()
+    leaf = rng.standard_normal(12000)
+    root = rng.standard_normal(3000)
+    l, r = dev(leaf), dev(root)
+    E.reduce(l, r, "sum", unit=unit(root))
+    torch.cuda.synchronize()
+    assert same_bits(host(r, root), oracle.reduce(3000, ire, ile, leaf, root, "sum"))
+
+
+def gpu_bcast_any(sf, root, leaf):
+    r, l = dev(root), dev(leaf)
+    sf.bcast(r, l, "replace", unit=unit(root))
+    torch.cuda.synchronize()
+    return host(l, leaf)
