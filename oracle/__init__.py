@@ -27,8 +27,8 @@ PAIR = np.dtype([("v", "<f8"), ("i", "<i4"), ("pad", "<i4")])
 # enum values of sf_oracle.h
 _DT = {np.dtype(np.float64): 0, np.dtype(np.float32): 1, np.dtype(np.int32): 2,
        np.dtype(np.int64): 3, PAIR: 4}
-REPLACE, SUM, MAX, MIN, MAXLOC = 0, 1, 2, 3, 4
-OPS = {"replace": REPLACE, "sum": SUM, "max": MAX, "min": MIN, "maxloc": MAXLOC}
+REPLACE, SUM, MAX, MIN, MAXLOC, MINLOC, PROD = 0, 1, 2, 3, 4, 5, 6
+OPS = {"replace": REPLACE, "sum": SUM, "max": MAX, "min": MIN, "maxloc": MAXLOC, "minloc": MINLOC, "prod": PROD}
 PW_TOPDOWN, PW_BOTTOMUP = 0, 1
 
 _lib = None

@@ -60,6 +60,13 @@ static int pair_better(const orc_pair *a, const orc_pair *b) {
   return a->i < b->i;
 }
 
+/* MINLOC: is a strictly better than b (smaller value, then smaller index)? */
+static int pair_better_min(const orc_pair *a, const orc_pair *b) {
+  if (less_f64(a->v, b->v)) return 1;
+  if (less_f64(b->v, a->v)) return 0;
+  return a->i < b->i;
+}
+
 /* dst = op(dst, src) for one element; dst is the left operand. */
 static void apply_op(int dtype, int op, void *dst, const void *src) {
   if (op == ORC_REPLACE) {
@@ -75,6 +82,7 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
     case ORC_F64: {
       double a = *(double *)dst, b = *(const double *)src;
       if (op == ORC_SUM) a = a + b;
+      else if (op == ORC_PROD) a = a * b;
       else if (op == ORC_MAX) a = less_f64(a, b) ? b : a;
       else if (op == ORC_MIN) a = less_f64(b, a) ? b : a;
       *(double *)dst = a;
@@ -83,6 +91,7 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
     case ORC_F32: {
       float a = *(float *)dst, b = *(const float *)src;
       if (op == ORC_SUM) a = a + b;
+      else if (op == ORC_PROD) a = a * b;
       else if (op == ORC_MAX) a = less_f32(a, b) ? b : a;
       else if (op == ORC_MIN) a = less_f32(b, a) ? b : a;
       *(float *)dst = a;
@@ -91,6 +100,7 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
     case ORC_I32: {
       int32_t a = *(int32_t *)dst, b = *(const int32_t *)src;
       if (op == ORC_SUM) a = (int32_t)((uint32_t)a + (uint32_t)b);
+      else if (op == ORC_PROD) a = (int32_t)((uint32_t)a * (uint32_t)b);
       else if (op == ORC_MAX) a = a < b ? b : a;
       else if (op == ORC_MIN) a = b < a ? b : a;
       *(int32_t *)dst = a;
@@ -99,6 +109,7 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
     case ORC_I64: {
       int64_t a = *(int64_t *)dst, b = *(const int64_t *)src;
       if (op == ORC_SUM) a = (int64_t)((uint64_t)a + (uint64_t)b);
+      else if (op == ORC_PROD) a = (int64_t)((uint64_t)a * (uint64_t)b);
       else if (op == ORC_MAX) a = a < b ? b : a;
       else if (op == ORC_MIN) a = b < a ? b : a;
       *(int64_t *)dst = a;
@@ -107,7 +118,7 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
     case ORC_PAIR: {
       orc_pair *a = (orc_pair *)dst;
       const orc_pair *b = (const orc_pair *)src;
-      if (op == ORC_MAXLOC && pair_better(b, a)) {
+      if ((op == ORC_MAXLOC && pair_better(b, a)) || (op == ORC_MINLOC && pair_better_min(b, a))) {
         a->v = b->v;
         a->i = b->i;
       }
@@ -117,8 +128,8 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
 }
 
 static int op_valid(int dtype, int op) {
-  if (dtype == ORC_PAIR) return op == ORC_REPLACE || op == ORC_MAXLOC;
-  return op == ORC_REPLACE || op == ORC_SUM || op == ORC_MAX || op == ORC_MIN;
+  if (dtype == ORC_PAIR) return op == ORC_REPLACE || op == ORC_MAXLOC || op == ORC_MINLOC;
+  return op == ORC_REPLACE || op == ORC_SUM || op == ORC_MAX || op == ORC_MIN || op == ORC_PROD;
 }
 
 static int check_graph(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
@@ -184,6 +195,18 @@ static float pw_f32_bottomup(const float *x, int64_t n) {
   return s;
 }
 
+/* The canonical pairwise tree with products instead of sums (top-down). */
+static double pwprod_f64(const double *x, int64_t n) {
+  if (n == 1) return x[0];
+  int64_t m = largest_pow2_below(n);
+  return pwprod_f64(x, m) * pwprod_f64(x + m, n - m);
+}
+static float pwprod_f32(const float *x, int64_t n) {
+  if (n == 1) return x[0];
+  int64_t m = largest_pow2_below(n);
+  return pwprod_f32(x, m) * pwprod_f32(x + m, n - m);
+}
+
 double orc_pairwise_f64(const double *x, int64_t n, int form) {
   if (n < 1) return 0.0;
   return form == ORC_PW_BOTTOMUP ? pw_f64_bottomup(x, n) : pw_f64_topdown(x, n);
@@ -246,18 +269,28 @@ int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int
     const int64_t *Lr = order + start[r];
     for (int c = 0; c < bs; c++) {
       char *dst = root + r * us + c * es;
-      if (op == ORC_SUM && (dtype == ORC_F64 || dtype == ORC_F32)) {
-        /* root + PW(leaves in ascending leaf index) */
+      if ((op == ORC_SUM || op == ORC_PROD) && (dtype == ORC_F64 || dtype == ORC_F32)) {
+        /* root op PW(leaves in ascending leaf index) */
         for (int64_t k = 0; k < deg; k++) {
           int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
           memcpy((char *)tmp + k * es, leaf + slot * us + c * es, (size_t)es);
         }
         if (dtype == ORC_F64) {
-          double t = orc_pairwise_f64((const double *)tmp, deg, pw_form);
-          *(double *)dst = *(double *)dst + t;
+          if (op == ORC_SUM) {
+            double t = orc_pairwise_f64((const double *)tmp, deg, pw_form);
+            *(double *)dst = *(double *)dst + t;
+          } else {
+            double t = pwprod_f64((const double *)tmp, deg);
+            *(double *)dst = *(double *)dst * t;
+          }
         } else {
-          float t = orc_pairwise_f32((const float *)tmp, deg, pw_form);
-          *(float *)dst = *(float *)dst + t;
+          if (op == ORC_SUM) {
+            float t = orc_pairwise_f32((const float *)tmp, deg, pw_form);
+            *(float *)dst = *(float *)dst + t;
+          } else {
+            float t = pwprod_f32((const float *)tmp, deg);
+            *(float *)dst = *(float *)dst * t;
+          }
         }
       } else {
         /* order-free ops (and REPLACE: the last leaf wins) folded in leaf order */

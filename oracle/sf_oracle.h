@@ -27,12 +27,12 @@
 extern "C" {
 #endif
 
-/* Element types.  ORC_PAIR is the MAXLOC pair {double v; int32 i; int32 pad}
+/* Element types.  ORC_PAIR is the MAXLOC / MINLOC pair {double v; int32 i; int32 pad}
  * with a 16-byte extent; pad is never read or written. */
 enum { ORC_F64 = 0, ORC_F32 = 1, ORC_I32 = 2, ORC_I64 = 3, ORC_PAIR = 4 };
 
 /* Operations (MPI_Op analogues, Section 3.2). */
-enum { ORC_REPLACE = 0, ORC_SUM = 1, ORC_MAX = 2, ORC_MIN = 3, ORC_MAXLOC = 4 };
+enum { ORC_REPLACE = 0, ORC_SUM = 1, ORC_MAX = 2, ORC_MIN = 3, ORC_MAXLOC = 4, ORC_MINLOC = 5, ORC_PROD = 6 };
 
 /* Forms of the canonical pairwise sum (see orc_pairwise_*). */
 enum { ORC_PW_TOPDOWN = 0, ORC_PW_BOTTOMUP = 1 };
@@ -50,9 +50,13 @@ int orc_bcast(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int6
  *   int SUM: two's-complement wrap-around
  *   MAX/MIN: total order with -0 < +0 (NaN never occurs in the inputs)
  *   MAXLOC : larger value wins, equal values -> smaller index wins
+ *   MINLOC : smaller value wins, equal values -> smaller index wins
+ *   FP PROD: root[r] = root[r] * PWprod(leaf[l_i] : i in L_r) (the same tree
+ *            as the sum, with products); int PROD: wrap-around
  *   REPLACE: the last leaf of L_r wins
  * Roots with an empty L_r are left untouched.  pw_form selects which of the
- * two equivalent formulations of PW is used (they must agree bitwise). */
+ * two equivalent formulations of PW is used (they must agree bitwise; PROD
+ * always uses the top-down form). */
 int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
                int dtype, int bs, int op, const void *leafdata, void *rootdata, int pw_form);
 

@@ -57,17 +57,19 @@ int orc_reduce_omp(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const
       const int64_t *Lr = order + start[r];
       for (int c = 0; c < bs; c++) {
         char *dst = root + r * us + c * es;
-        if (op == ORC_SUM && (dtype == ORC_F64 || dtype == ORC_F32)) {
+        if ((op == ORC_SUM || op == ORC_PROD) && (dtype == ORC_F64 || dtype == ORC_F32)) {
           for (int64_t k = 0; k < deg; k++) {
             int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
             memcpy((char *)tmp + k * es, leaf + slot * us + c * es, (size_t)es);
           }
           if (dtype == ORC_F64) {
-            double t = orc_pairwise_f64((const double *)tmp, deg, ORC_PW_TOPDOWN);
-            *(double *)dst = *(double *)dst + t;
+            double t = op == ORC_SUM ? orc_pairwise_f64((const double *)tmp, deg, ORC_PW_TOPDOWN)
+                                     : pwprod_f64((const double *)tmp, deg);
+            *(double *)dst = op == ORC_SUM ? *(double *)dst + t : *(double *)dst * t;
           } else {
-            float t = orc_pairwise_f32((const float *)tmp, deg, ORC_PW_TOPDOWN);
-            *(float *)dst = *(float *)dst + t;
+            float t = op == ORC_SUM ? orc_pairwise_f32((const float *)tmp, deg, ORC_PW_TOPDOWN)
+                                    : pwprod_f32((const float *)tmp, deg);
+            *(float *)dst = op == ORC_SUM ? *(float *)dst + t : *(float *)dst * t;
           }
         } else {
           for (int64_t k = 0; k < deg; k++) {

@@ -261,6 +261,94 @@ def test_reduce_maxloc_bruteforce(orc, ties):
     assert (got["pad"] == 55).all()      # padding is never written
 
 
+def minloc_bruteforce(root, leaf_units, iroot):
+    """Per root, the lexicographic best of {root} U leaves: min v, then min i."""
+    out = root.copy()
+    for r in range(root.size):
+        cand = np.concatenate([root[r:r + 1], leaf_units[iroot == r]])
+        order = np.lexsort((cand["i"], cand["v"]))
+        out[r]["v"], out[r]["i"] = cand[order[0]]["v"], cand[order[0]]["i"]
+    return out
+
+
+@pytest.mark.parametrize("ties", [False, True])
+def test_reduce_minloc_bruteforce(orc, ties):
+    rng = np.random.default_rng(113)
+    nroots, nleaves = 40, 3000
+    iroot = rng.integers(0, nroots, size=nleaves)
+    leaf = inputs.maxloc_leaves(rng, nleaves, ties)
+    root = inputs.maxloc_roots(rng, nroots, ties)
+    leaf["pad"] = 77
+    root["pad"] = 55
+    got = orc.reduce(nroots, iroot, None, leaf, root, "minloc")
+    want = minloc_bruteforce(root, leaf, iroot)
+    assert np.array_equal(got["v"], want["v"]) and np.array_equal(got["i"], want["i"])
+    assert (got["pad"] == 55).all()
+    # MINLOC of the values is MAXLOC of their negations (with the same index rule)
+    neg_l, neg_r = leaf.copy(), root.copy()
+    neg_l["v"], neg_r["v"] = -leaf["v"], -root["v"]
+    mx = orc.reduce(nroots, iroot, None, neg_l, neg_r, "maxloc")
+    assert np.array_equal(mx["i"], got["i"]) and np.array_equal(-mx["v"], got["v"])
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_reduce_int_prod_wraps_like_numpy_multiply_at(orc, dtype):
+    rng = np.random.default_rng(111)
+    info = np.iinfo(dtype)
+    for nroots, nleaves in [(1, 1000), (7, 5000), (100, 3000)]:
+        iroot = rng.integers(0, nroots, size=nleaves)
+        leaf = rng.integers(info.min, info.max, size=nleaves, dtype=dtype, endpoint=True) | 1
+        root = rng.integers(info.min, info.max, size=nroots, dtype=dtype, endpoint=True)
+        want = root.copy()
+        np.multiply.at(want, iroot, leaf)
+        got = orc.reduce(nroots, iroot, None, leaf, root, "prod")
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype,e", [(np.float64, 500), (np.float32, 50)])
+def test_reduce_fp_prod_tree_closed_forms(orc, dtype, e):
+    """FP PROD uses the pairwise tree of the sum, in leaf order, with the root
+    multiplied in last.  Powers of two make every product exact unless it
+    overflows, which exposes the grouping:
+      leaves [2^e, 2^e, 2^2e, 2^-2e]: tree (x0 x1)(x2 x3) = 2^2e, while the
+      leaf-order running product overflows at x0 x1 x2;
+      root 2^-2e, leaves [2^2e, 2^2e]: root * (x0 x1) = 2^-2e * inf = inf,
+      while folding the root in first gives 2^2e."""
+    f = lambda k: dtype(2.0) ** dtype(k)
+    leaves = np.array([f(e), f(e), f(2 * e), f(-2 * e)], dtype=dtype)
+    out = orc.reduce(1, [0, 0, 0, 0], None, leaves, np.array([1.0], dtype), "prod")
+    assert out[0] == f(2 * e)
+    with np.errstate(over="ignore"):
+        assert np.isinf(dtype(leaves[0] * leaves[1]) * leaves[2])     # the sequential order would overflow
+    # leaf order, not slot order: the same values reversed by ilocal
+    out = orc.reduce(1, [0, 0, 0, 0], [3, 2, 1, 0], leaves[::-1].copy(), np.array([1.0], dtype), "prod")
+    assert out[0] == f(2 * e)
+    with np.errstate(over="ignore", invalid="ignore"):
+        out = orc.reduce(1, [0, 0], None, np.array([f(2 * e), f(2 * e)], dtype), np.array([f(-2 * e)], dtype), "prod")
+    assert np.isinf(out[0]) and out[0] > 0
+    # n leaves of 2 on root 3: 3 * 2^n exactly, for every n up to the exponent range
+    for n in (1, 2, 3, 5, 17, 100):
+        out = orc.reduce(1, [0] * n, None, np.full(n, 2.0, dtype), np.array([3.0], dtype), "prod")
+        assert out[0] == dtype(3.0) * f(n)
+
+
+@pytest.mark.parametrize("n", [3, 64, 1000, 4097])
+def test_reduce_fp_prod_error_bound(orc, n):
+    """|PWprod - exact| <= gamma_n |exact| for n leaves and one root factor
+    (n roundings, each of relative size <= u; Higham ch. 3).  The exact
+    product comes from Fraction arithmetic."""
+    rng = np.random.default_rng(n)
+    for dtype, u in [(np.float64, U64), (np.float32, 2.0 ** -24)]:
+        x = (1.0 + 1e-3 * rng.standard_normal(n)).astype(dtype)
+        r0 = dtype(1.5)
+        got = float(orc.reduce(1, [0] * n, None, x, np.array([r0], dtype), "prod")[0])
+        exact = Fraction(float(r0))
+        for v in x:
+            exact *= Fraction(float(v))
+        g = n * u / (1 - n * u)
+        assert abs(Fraction(got) - exact) <= Fraction(g) * abs(exact)
+
+
 def test_reduce_replace_last_leaf_wins(orc):
     rng = np.random.default_rng(14)
     nroots, nleaves = 30, 500
@@ -504,6 +592,46 @@ def test_bcast_pair_units(orc):
     want["i"][g.ilocal] = np.where(take, ri, li)
     assert np.any(take) and np.any(~take) and np.any((rv == lv) & (ri != li))
     assert got.tobytes() == want.tobytes()
+
+
+def test_bcast_pair_minloc(orc):
+    """Bcast MINLOC keeps, per leaf, the smaller value of leaf and root (-0
+    below +0), ties going to the smaller index -- written out with NumPy."""
+    g = inputs.single_sf(seed=47, nroots=400, nleaves=1500, leafspace=1800)
+    rng = np.random.default_rng(48)
+    root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    root["i"] = rng.integers(0, 50, g.nroots)
+    leaf = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    leaf["i"] = rng.integers(0, 50, g.leafspace)
+    leaf["pad"] = 77
+    got = orc.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, "minloc")
+    lv, li = leaf["v"][g.ilocal], leaf["i"][g.ilocal]
+    rv, ri = root["v"][g.iroot], root["i"][g.iroot]
+    lt = (rv < lv) | ((rv == lv) & np.signbit(rv) & ~np.signbit(lv))
+    eq = (rv == lv) & (np.signbit(rv) == np.signbit(lv))
+    take = lt | (eq & (ri < li))
+    want = leaf.copy()
+    want["v"][g.ilocal] = np.where(take, rv, lv)
+    want["i"][g.ilocal] = np.where(take, ri, li)
+    assert np.any(take) and np.any(~take) and np.any((rv == lv) & (ri != li))
+    assert got.tobytes() == want.tobytes()
+
+
+def test_omp_prod_minloc_equal_sequential(orc):
+    g = inputs.spmv_ghost(seed=49, nroots=2000, nleaves=40001)
+    rng = np.random.default_rng(50)
+    for dtype in (np.float64, np.float32, np.int32, np.int64):
+        leaf = (1.0 + 1e-3 * rng.standard_normal(g.nleaves)).astype(dtype) if np.dtype(dtype).kind == "f" \
+            else rng.integers(-9, 10, g.nleaves).astype(dtype)
+        root = np.ones(g.nroots, dtype)
+        a = orc.reduce(g.nroots, g.iroot, None, leaf, root, "prod")
+        b = orc.reduce_omp(g.nroots, g.iroot, None, leaf, root, "prod")
+        assert a.tobytes() == b.tobytes(), dtype
+    leaf = inputs.maxloc_leaves(rng, g.nleaves, ties=True)
+    root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    a = orc.reduce(g.nroots, g.iroot, None, leaf, root, "minloc")
+    b = orc.reduce_omp(g.nroots, g.iroot, None, leaf, root, "minloc")
+    assert np.array_equal(a["v"].view(np.uint64), b["v"].view(np.uint64)) and np.array_equal(a["i"], b["i"])
 
 
 # ------------------------------------------------ multi-SF, Gather, Scatter
