@@ -66,21 +66,25 @@ typedef enum {
   SF_OWN_POINTER = 2  /* not supported: returns SF_ERR_UNSUPPORTED */
 } sf_copymode;
 
-/* Element type of a unit.  SF_F64_I32 is the MAXLOC pair
+/* Element type of a unit.  SF_F64_I32 is the MAXLOC / MINLOC pair
  * struct { double v; int32_t i; int32_t pad; } with a 16-byte extent; pad
  * never affects a result and is never written in the caller's roots or leaves
  * (large SFs copy whole 16-byte leaf units, pad included, into scratch). */
 typedef enum { SF_F64 = 0, SF_F32 = 1, SF_I32 = 2, SF_I64 = 3, SF_F64_I32 = 4 } sf_dtype;
 
 /* A unit is bs contiguous elements of one dtype: the "unit" MPI datatype of
- * Section 3.2.  Ops act per element (MAXLOC: per pair). */
+ * Section 3.2.  Ops act per element (MAXLOC / MINLOC: per pair). */
 typedef struct {
   int32_t dtype; /* sf_dtype */
   int32_t bs;    /* block size, >= 1 */
 } sf_unit;
 
-/* Operation (MPI_Op of Section 3.2). */
-typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4 } sf_op;
+/* Operation (MPI_Op of Section 3.2, which names the MPI reductions as the
+ * ops of Bcast and Reduce).  SUM, MAX, MIN and PROD act on F64, F32, I32 and
+ * I64 (integers wrap around); MAXLOC and MINLOC on F64_I32 pairs.  PROD and
+ * MINLOC have no native device atomic: they combine through the
+ * deterministic kernels in every reduce mode. */
+typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4, SF_MINLOC = 5, SF_PROD = 6 } sf_op;
 
 /* How SFReduce combines leaves of a root that has several (Section 5.3 uses
  * atomics when destinations repeat).
@@ -92,10 +96,13 @@ typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4
  *                  root whose leaves all fall in one window is updated
  *                  plainly and a root spanning windows takes one native
  *                  atomic per window (FetchAndOp: a returning atomic add);
- *                  FP SUM order is unspecified;
+ *                  FP SUM order is unspecified (PROD, MAXLOC in some
+ *                  configurations and MINLOC stay deterministic);
  *  DETERMINISTIC : root-sorted segmented reduction; FP SUM is the
  *                  canonical pairwise sum of the root's leaves in ascending
- *                  leaf index, added to the root (root on the left);
+ *                  leaf index, added to the root (root on the left); FP
+ *                  PROD the same tree with products, the root multiplied
+ *                  last;
  *                  bit-identical for every launch configuration.
  * Roots with a single leaf never need atomics. */
 typedef enum { SF_REDUCE_AUTO = 0, SF_REDUCE_ATOMIC = 1, SF_REDUCE_DETERMINISTIC = 2 } sf_reduce_mode;
@@ -196,7 +203,7 @@ int sf_set_reduce_mode(sf_t sf, int32_t mode);
 
 /* SFBcast (Section 3.2, item 1): root -> leaves.  For every leaf i,
  * leafdata[l_i] = rootdata[r_i] (REPLACE) or op(leafdata[l_i], rootdata[r_i])
- * (SUM, MAX, MIN; MAXLOC on F64_I32).  Holes are not touched.
+ * (SUM, MAX, MIN, PROD; MAXLOC, MINLOC on F64_I32).  Holes are not touched.
  *  rootdata: [nroots] units; leafdata: [leafspace] units. */
 int sf_bcast_begin(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, int32_t op,
                    hipStream_t stream);
@@ -207,7 +214,8 @@ int sf_bcast_end(sf_t sf, sf_unit unit, const void *rootdata, void *leafdata, in
  * own value taking part (Section 4.1 adds B^T x back onto y).  Roots without
  * leaves are not touched.  REPLACE: the last leaf in leaf order wins
  * (deterministic mode; in atomic mode some leaf wins).  MAXLOC: larger
- * value wins, equal values go to the smaller index.  MAX/MIN order -0 < +0.
+ * value wins, MINLOC: smaller value wins, equal values going to the smaller
+ * index in both.  MAX/MIN (and the pairs' values) order -0 < +0.
  *  leafdata: [leafspace] units; rootdata: [nroots] units. */
 int sf_reduce_begin(sf_t sf, sf_unit unit, const void *leafdata, void *rootdata, int32_t op,
                     hipStream_t stream);

@@ -124,9 +124,10 @@ static int begin_common(sf_t sf, int kind, sf_unit unit, int32_t op, const void 
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != sf->device) return SF_ERR_ARG;  // plan lives on sf->device
   if (!valid_unit(unit)) return SF_ERR_ARG;
-  if (op < SF_REPLACE || op > SF_MAXLOC) return SF_ERR_ARG;
-  if (op == SF_MAXLOC && unit.dtype != SF_F64_I32) return SF_ERR_UNSUPPORTED;
-  if (unit.dtype == SF_F64_I32 && op != SF_MAXLOC && op != SF_REPLACE) return SF_ERR_UNSUPPORTED;
+  if (op < SF_REPLACE || op > SF_PROD) return SF_ERR_ARG;
+  const bool loc = op == SF_MAXLOC || op == SF_MINLOC;
+  if (loc && unit.dtype != SF_F64_I32) return SF_ERR_UNSUPPORTED;
+  if (unit.dtype == SF_F64_I32 && !loc && op != SF_REPLACE) return SF_ERR_UNSUPPORTED;
   const int es = elem_size(unit.dtype);
   if (sf->nleaves > 0) {
     if (!a || !b || (kind == 2 && !c)) return SF_ERR_ARG;

@@ -36,7 +36,20 @@ __device__ __forceinline__ float fkey_inv(uint32_t k) {
   return __int_as_float((int)(k & 0x80000000u ? k & 0x7fffffffu : ~k));
 }
 
-enum OpCode { OP_REPLACE = SF_REPLACE, OP_SUM = SF_SUM, OP_MAX = SF_MAX, OP_MIN = SF_MIN, OP_MAXLOC = SF_MAXLOC };
+enum OpCode {
+  OP_REPLACE = SF_REPLACE,
+  OP_SUM = SF_SUM,
+  OP_MAX = SF_MAX,
+  OP_MIN = SF_MIN,
+  OP_MAXLOC = SF_MAXLOC,
+  OP_MINLOC = SF_MINLOC,
+  OP_PROD = SF_PROD
+};
+// Ops with a native device atomic on the scalar types (the others -- the
+// location pairs and the product -- always combine through the
+// deterministic kernels).
+template <int OP>
+constexpr bool kHasAtomic = OP == OP_SUM || OP == OP_MAX || OP == OP_MIN;
 
 // a (left operand) op b
 template <int OP, typename T>
@@ -46,6 +59,7 @@ template <int OP>
 struct Op<OP, double> {
   static __device__ __forceinline__ double apply(double a, double b) {
     if (OP == OP_SUM) return a + b;
+    if (OP == OP_PROD) return a * b;
     if (OP == OP_MAX) return fkey(a) < fkey(b) ? b : a;
     if (OP == OP_MIN) return fkey(b) < fkey(a) ? b : a;
     return b;
@@ -55,6 +69,7 @@ template <int OP>
 struct Op<OP, float> {
   static __device__ __forceinline__ float apply(float a, float b) {
     if (OP == OP_SUM) return a + b;
+    if (OP == OP_PROD) return a * b;
     if (OP == OP_MAX) return fkey(a) < fkey(b) ? b : a;
     if (OP == OP_MIN) return fkey(b) < fkey(a) ? b : a;
     return b;
@@ -64,6 +79,7 @@ template <int OP>
 struct Op<OP, int32_t> {
   static __device__ __forceinline__ int32_t apply(int32_t a, int32_t b) {
     if (OP == OP_SUM) return (int32_t)((uint32_t)a + (uint32_t)b);
+    if (OP == OP_PROD) return (int32_t)((uint32_t)a * (uint32_t)b);
     if (OP == OP_MAX) return a < b ? b : a;
     if (OP == OP_MIN) return b < a ? b : a;
     return b;
@@ -73,6 +89,7 @@ template <int OP>
 struct Op<OP, int64_t> {
   static __device__ __forceinline__ int64_t apply(int64_t a, int64_t b) {
     if (OP == OP_SUM) return (int64_t)((uint64_t)a + (uint64_t)b);
+    if (OP == OP_PROD) return (int64_t)((uint64_t)a * (uint64_t)b);
     if (OP == OP_MAX) return a < b ? b : a;
     if (OP == OP_MIN) return b < a ? b : a;
     return b;
@@ -96,9 +113,9 @@ struct Op<OP, uint32_t> {
 template <int OP>
 struct Op<OP, Pair> {
   static __device__ __forceinline__ Pair apply(Pair a, Pair b) {
-    if (OP == OP_MAXLOC) {
+    if (OP == OP_MAXLOC || OP == OP_MINLOC) {
       const uint64_t ka = fkey(a.v), kb = fkey(b.v);
-      const bool better = kb > ka || (kb == ka && b.i < a.i);
+      const bool better = (OP == OP_MAXLOC ? kb > ka : kb < ka) || (kb == ka && b.i < a.i);
       return better ? b : a;
     }
     return b;

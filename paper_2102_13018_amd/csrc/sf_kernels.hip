@@ -595,6 +595,7 @@ static int bcast_op_t(sf_s *sf, int bs, int op, const void *root, void *leaf, hi
     case SF_SUM: SF_BOP(OP_SUM); break;
     case SF_MAX: SF_BOP(OP_MAX); break;
     case SF_MIN: SF_BOP(OP_MIN); break;
+    case SF_PROD: SF_BOP(OP_PROD); break;
     default: return SF_ERR_UNSUPPORTED;
   }
 #undef SF_BOP
@@ -643,6 +644,9 @@ int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, h
       const unsigned g = (unsigned)sf->hp.tiles.size();
       if (op == SF_MAXLOC)
         hipLaunchKernelGGL((k_bcast_op<Pair, OP_MAXLOC>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx,
+                           d.lidx, (const Pair *)root, (Pair *)leaf, unit.bs);
+      else if (op == SF_MINLOC)
+        hipLaunchKernelGGL((k_bcast_op<Pair, OP_MINLOC>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx,
                            d.lidx, (const Pair *)root, (Pair *)leaf, unit.bs);
       else if (op == SF_REPLACE)
         hipLaunchKernelGGL((k_bcast_op<Pair, OP_REPLACE>), dim3(g), dim3(kBlock), 0, st, d.segs, d.tiles, d.ridx,
@@ -786,6 +790,9 @@ static int reduce_t(sf_s *sf, int op, int mode, const void *leafv, void *rootv, 
     case SF_SUM: SF_RED(OP_SUM);
     case SF_MAX: SF_RED(OP_MAX);
     case SF_MIN: SF_RED(OP_MIN);
+    case SF_PROD:  // no native atomic multiply: deterministic in every mode
+      if (!dup) return reduce_plain_t<T, OP_PROD>(sf, leaf, root, bs, st);
+      return reduce_det_t<T, OP_PROD>(sf, leaf, root, bs, st);
     default: return SF_ERR_UNSUPPORTED;
   }
 #undef SF_RED
@@ -807,6 +814,10 @@ int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, 
       if (op == SF_REPLACE) {
         if (!sf->has_dup_roots) return reduce_plain_t<Pair, OP_REPLACE>(sf, l, r, unit.bs, st);
         return reduce_det_t<Pair, OP_REPLACE>(sf, l, r, unit.bs, st);
+      }
+      if (op == SF_MINLOC) {  // no atomic form: deterministic in every mode
+        if (!sf->has_dup_roots) return reduce_plain_t<Pair, OP_MINLOC>(sf, l, r, unit.bs, st);
+        return reduce_det_t<Pair, OP_MINLOC>(sf, l, r, unit.bs, st);
       }
       if (op != SF_MAXLOC) return SF_ERR_UNSUPPORTED;
       if (!sf->has_dup_roots) return reduce_plain_t<Pair, OP_MAXLOC>(sf, l, r, unit.bs, st);

@@ -433,10 +433,22 @@ __device__ __forceinline__ void win_load_key(V *lds, const T *__restrict__ scr, 
 // deterministic floating-point sums keep the canonical pairwise tree.
 template <typename V, int OP>
 struct OrderFree {
-  static constexpr bool value =
-      OP == OP_MAX || OP == OP_MIN || OP == OP_MAXLOC || (OP == OP_SUM && std::is_integral<V>::value);
-  static constexpr bool idempotent = OP != OP_SUM;
+  static constexpr bool value = OP == OP_MAX || OP == OP_MIN || OP == OP_MAXLOC || OP == OP_MINLOC ||
+                                ((OP == OP_SUM || OP == OP_PROD) && std::is_integral<V>::value);
+  static constexpr bool idempotent = OP != OP_SUM && OP != OP_PROD;
 };
+// What fills the positions past the end of a run of elements whose first
+// element is e0: e0 itself for an idempotent op, else the op's neutral
+// element (0 for the sum, 1 for the product).
+template <typename V, int OP>
+__device__ __forceinline__ V free_pad(V e0) {
+  if constexpr (OrderFree<V, OP>::idempotent)
+    return e0;
+  else if constexpr (OP == OP_PROD)
+    return V(1);
+  else
+    return V{};
+}
 
 // Lane steps of the canonical chunk tree (lane l holds the tree of its LPT
 // leaves; lanes combine at distances 1, 2, ..., 32 while the partner's block
@@ -462,12 +474,11 @@ __device__ __forceinline__ V wave_tree(V v, int lane, int n) {
 
 // A whole root of an order-free op (or of any op in atomic mode): its n
 // elements four at a time (loads in flight, one accumulator); positions past
-// n repeat the first element (an idempotent op ignores it) or add the sum's
-// zero.
+// n take free_pad.
 template <typename V, int OP>
 __device__ __forceinline__ V small_free(const V *lds, int o, int n, int bs, int c) {
   const V e0 = ld(lds + o * bs + c);
-  const V pad = OrderFree<V, OP>::idempotent ? e0 : V{};
+  const V pad = free_pad<V, OP>(e0);
   V a = e0;
   for (int e = 1; e < n; e += 4) {
     V x[4];
@@ -529,10 +540,8 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
     if constexpr (kFree) {
       const int o0 = wc_off(onf);
       for (int c = 0; c < bs; c++) {
-        // lanes past the chunk's end take its first element (a repeat that
-        // an idempotent op ignores) or the sum's zero
-        V a = lane < n ? ld(lds + (o0 + lane) * bs + c)
-                       : (OrderFree<V, OP>::idempotent ? ld(lds + o0 * bs + c) : V{});
+        // lanes past the chunk's end take free_pad of its first element
+        V a = lane < n ? ld(lds + (o0 + lane) * bs + c) : free_pad<V, OP>(ld(lds + o0 * bs + c));
 #pragma unroll
         for (int s = 1; s < LPT; s++)
           if (s * 64 + lane < n) a = Op<OP, V>::apply(a, ld(lds + (o0 + s * 64 + lane) * bs + c));
@@ -1023,14 +1032,15 @@ static size_t hot_prefix_bytes(const sf_s *sf, size_t ub) {
   return ((size_t)h.hx_e0.back() * ub + 255) / 256 * 256;
 }
 
-// Whether a partitioned Reduce of op OP on T takes the hot path: any op in
-// atomic mode, and in deterministic mode the ops whose result does not
-// depend on the order of combination.  MAXLOC (no native atomic for pass B)
-// and the deterministic floating-point sum (its canonical pairwise trees)
-// keep their hot roots in the windows.
+// Whether a partitioned Reduce of op OP on T takes the hot path: the ops
+// with a native atomic for pass B (SUM, MAX, MIN) in atomic mode, and in
+// deterministic mode those whose result does not depend on the order of
+// combination.  The location pairs and the product (no native atomic) and
+// the deterministic floating-point sum (its canonical pairwise trees) keep
+// their hot roots in the windows.
 template <typename T, int OP>
 static bool reduce_takes_hot(const sf_s *sf, bool atomic) {
-  if (!sf->hp.hot || OP == OP_MAXLOC || OP == OP_REPLACE) return false;
+  if (!sf->hp.hot || !kHasAtomic<OP>) return false;
   return atomic || OP == OP_MAX || OP == OP_MIN || std::is_integral<T>::value;
 }
 
@@ -1082,7 +1092,7 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   T *scr = (T *)s;
   T *buf[2] = {(T *)((char *)s + main_bytes), (T *)((char *)s + main_bytes + lvl)};
   const PassBLds pl = passb_lds(hs, ub);
-  if constexpr (OP != OP_MAXLOC && OP != OP_REPLACE) {
+  if constexpr (kHasAtomic<OP>) {
     if (hot) {
       // cold roots through their windows (root updates as in atomic mode:
       // exact for the ops that take this path in deterministic mode), hot
@@ -1102,7 +1112,7 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
   rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   const unsigned gw = (unsigned)hs.win.size();
-  if constexpr (OP != OP_MAXLOC) {
+  if constexpr (kHasAtomic<OP>) {
     if (atomic) {
       rc = sp_reduce_launch<T, OP, true>(gw, pl, st, ds.win, ds.sroot, ds.wchunk, ds.lpos, (const T *)scr,
                                          buf[0], root, bs);
@@ -1206,7 +1216,12 @@ template int launch_reduce_part<int32_t, OP_MIN>(sf_s *, const int32_t *, int32_
 template int launch_reduce_part<int64_t, OP_SUM>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
 template int launch_reduce_part<int64_t, OP_MAX>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
 template int launch_reduce_part<int64_t, OP_MIN>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
+template int launch_reduce_part<double, OP_PROD>(sf_s *, const double *, double *, int, bool, hipStream_t);
+template int launch_reduce_part<float, OP_PROD>(sf_s *, const float *, float *, int, bool, hipStream_t);
+template int launch_reduce_part<int32_t, OP_PROD>(sf_s *, const int32_t *, int32_t *, int, bool, hipStream_t);
+template int launch_reduce_part<int64_t, OP_PROD>(sf_s *, const int64_t *, int64_t *, int, bool, hipStream_t);
 template int launch_reduce_part<Pair, OP_MAXLOC>(sf_s *, const Pair *, Pair *, int, bool, hipStream_t);
+template int launch_reduce_part<Pair, OP_MINLOC>(sf_s *, const Pair *, Pair *, int, bool, hipStream_t);
 template int launch_fop_part<int32_t>(sf_s *, int32_t *, const int32_t *, int32_t *, int, bool, hipStream_t);
 template int launch_fop_part<int64_t>(sf_s *, int64_t *, const int64_t *, int64_t *, int, bool, hipStream_t);
 template int launch_fop_part<double>(sf_s *, double *, const double *, double *, int, bool, hipStream_t);

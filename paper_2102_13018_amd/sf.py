@@ -14,7 +14,7 @@ _SO = os.path.join(_HERE, "libsf.so")
 
 # enums of sf.h
 SF_F64, SF_F32, SF_I32, SF_I64, SF_F64_I32 = 0, 1, 2, 3, 4
-SF_REPLACE, SF_SUM, SF_MAX, SF_MIN, SF_MAXLOC = 0, 1, 2, 3, 4
+SF_REPLACE, SF_SUM, SF_MAX, SF_MIN, SF_MAXLOC, SF_MINLOC, SF_PROD = 0, 1, 2, 3, 4, 5, 6
 SF_REDUCE_AUTO, SF_REDUCE_ATOMIC, SF_REDUCE_DETERMINISTIC = 0, 1, 2
 SF_COPY_VALUES, SF_USE_POINTER, SF_OWN_POINTER = 0, 1, 2
 SF_KIND_BCAST, SF_KIND_REDUCE, SF_KIND_FETCH_AND_OP = 0, 1, 2
@@ -23,7 +23,8 @@ ERRORS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_DUP_LEAF", -3: "SF_ERR_NOT_S
           -4: "SF_ERR_UNSUPPORTED", -5: "SF_ERR_HIP", -6: "SF_ERR_OOM", -7: "SF_ERR_MISMATCH",
           -8: "SF_ERR_BUSY", -9: "SF_ERR_SCRATCH"}
 SF_NOALLOC_SCRATCH_BYTES = 64 << 20
-OPS = {"replace": SF_REPLACE, "sum": SF_SUM, "max": SF_MAX, "min": SF_MIN, "maxloc": SF_MAXLOC}
+OPS = {"replace": SF_REPLACE, "sum": SF_SUM, "max": SF_MAX, "min": SF_MIN, "maxloc": SF_MAXLOC,
+       "minloc": SF_MINLOC, "prod": SF_PROD}
 MODES = {"auto": SF_REDUCE_AUTO, "atomic": SF_REDUCE_ATOMIC, "deterministic": SF_REDUCE_DETERMINISTIC}
 ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16}
 
