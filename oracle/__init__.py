@@ -7,7 +7,8 @@ baseline use this package; the product path never imports it, and it shares
 no code with the GPU library.
 
 Data are NumPy arrays of units: shape ``[n]`` (bs = 1) or ``[n, bs]``, with
-dtype float64 / float32 / int32 / int64, or :data:`PAIR` (the MAXLOC unit
+dtype float64 / float32 / int32 / int64 / float16, :data:`BF16` (bfloat16
+bit patterns), or :data:`PAIR` (the MAXLOC / MINLOC unit
 ``{double v; int32 i; int32 pad}``, 16-byte extent).
 
 Every wrapper is functional: it copies its data arguments and returns new
@@ -23,10 +24,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
 PAIR = np.dtype([("v", "<f8"), ("i", "<i4"), ("pad", "<i4")])
+# bfloat16 units: NumPy has no such type, so their 16-bit patterns travel in
+# a one-field structured dtype (binary16 units are plain np.float16)
+BF16 = np.dtype([("bf16", "<u2")])
 
 # enum values of sf_oracle.h
 _DT = {np.dtype(np.float64): 0, np.dtype(np.float32): 1, np.dtype(np.int32): 2,
-       np.dtype(np.int64): 3, PAIR: 4}
+       np.dtype(np.int64): 3, PAIR: 4, np.dtype(np.float16): 5, BF16: 6}
 REPLACE, SUM, MAX, MIN, MAXLOC, MINLOC, PROD = 0, 1, 2, 3, 4, 5, 6
 OPS = {"replace": REPLACE, "sum": SUM, "max": MAX, "min": MIN, "maxloc": MAXLOC, "minloc": MINLOC, "prod": PROD}
 PW_TOPDOWN, PW_BOTTOMUP = 0, 1
@@ -73,6 +77,10 @@ def lib():
         L.orc_pairwise_f64.restype = ctypes.c_double
         L.orc_pairwise_f32.argtypes = [p, i64, ci]
         L.orc_pairwise_f32.restype = ctypes.c_float
+        for f in (L.orc_to_f16, L.orc_to_bf16):
+            f.argtypes, f.restype = [ctypes.c_double], ctypes.c_uint16
+        for f in (L.orc_from_f16, L.orc_from_bf16):
+            f.argtypes, f.restype = [ctypes.c_uint16], ctypes.c_double
         _lib = L
     return _lib
 
@@ -346,3 +354,21 @@ def embedded_leaf(sf, slots):
     sel = set(int(s) for s in slots)
     keep = [k for k in range(len(ir)) if int(il[k]) in sel]
     return n, ir[keep], il[keep], rk[keep]
+
+
+def to_f16(x):
+    """Bit pattern of x rounded to binary16 (nearest, ties to even)."""
+    return int(lib().orc_to_f16(float(x)))
+
+
+def to_bf16(x):
+    """Bit pattern of x rounded to bfloat16 (nearest, ties to even)."""
+    return int(lib().orc_to_bf16(float(x)))
+
+
+def from_f16(h):
+    return float(lib().orc_from_f16(int(h)))
+
+
+def from_bf16(h):
+    return float(lib().orc_from_bf16(int(h)))

@@ -37,9 +37,77 @@ static int64_t elem_size(int dtype) {
     case ORC_I32: return 4;
     case ORC_I64: return 8;
     case ORC_PAIR: return 16;
+    case ORC_F16: return 2;
+    case ORC_BF16: return 2;
     default: return -1;
   }
 }
+
+/* ------------------------------------------------ 16-bit binary formats */
+/* A binary floating-point format with p significand bits (the leading one
+ * included), w exponent bits and bias = 2^(w-1) - 1: normal numbers
+ * (1.f) 2^E for E in [1 - bias, bias], subnormals f 2^(1 - bias - (p - 1)).
+ * binary16: p 11, w 5; bfloat16: p 8, w 8 (IEEE 754-2008, Section 3). */
+typedef struct {
+  int p, w;
+} orc_fmt;
+static const orc_fmt FMT_F16 = {11, 5};
+static const orc_fmt FMT_BF16 = {8, 8};
+
+static double fmt_decode(orc_fmt f, uint16_t h) {
+  const int bias = (1 << (f.w - 1)) - 1, fb = f.p - 1;
+  const int ex = (h >> fb) & ((1 << f.w) - 1);
+  const double m = (double)(h & ((1u << fb) - 1));
+  double v;
+  if (ex == 0)
+    v = ldexp(m, 1 - bias - fb);
+  else if (ex == (1 << f.w) - 1)
+    v = m != 0 ? NAN : INFINITY;
+  else
+    v = ldexp(m + ldexp(1.0, fb), ex - bias - fb);
+  return (h >> 15) & 1 ? -v : v;
+}
+
+/* The representable value nearest to x (ties to the even significand),
+ * +-infinity when that exceeds the largest finite value: scale |x| so that
+ * the format's last significand place is 1, round to an integer, scale back.
+ * The quantum is 2^(E - (p - 1)) for |x| in [2^E, 2^(E+1)), never below the
+ * subnormal quantum. */
+static double fmt_round(orc_fmt f, double x) {
+  const int bias = (1 << (f.w - 1)) - 1, fb = f.p - 1;
+  if (x == 0 || isnan(x) || isinf(x)) return x;
+  int e;
+  (void)frexp(fabs(x), &e); /* |x| in [2^(e-1), 2^e) */
+  int q = (e - 1) - fb;
+  if (q < 1 - bias - fb) q = 1 - bias - fb;
+  const double r = nearbyint(ldexp(fabs(x), -q)); /* exact scaling; default mode: ties to even */
+  double v = ldexp(r, q);
+  if (v >= ldexp(1.0, bias + 1)) v = INFINITY;
+  return signbit(x) ? -v : v;
+}
+
+static uint16_t fmt_encode(orc_fmt f, double x) {
+  const int bias = (1 << (f.w - 1)) - 1, fb = f.p - 1;
+  const double v = fmt_round(f, x);
+  const uint16_t sign = signbit(v) ? 0x8000 : 0;
+  const double a = fabs(v);
+  if (isnan(v)) return (uint16_t)(((1u << f.w) - 1) << fb | 1u << (fb - 1));
+  if (isinf(v)) return (uint16_t)(sign | ((1u << f.w) - 1) << fb);
+  if (a < ldexp(1.0, 1 - bias)) return (uint16_t)(sign | (uint16_t)ldexp(a, bias - 1 + fb)); /* subnormal or 0 */
+  int e;
+  (void)frexp(a, &e);
+  const int E = e - 1;
+  const uint32_t mant = (uint32_t)(ldexp(a, -E) * ldexp(1.0, fb)) - (1u << fb);
+  return (uint16_t)(sign | (uint32_t)(E + bias) << fb | mant);
+}
+
+uint16_t orc_to_f16(double x) { return fmt_encode(FMT_F16, x); }
+uint16_t orc_to_bf16(double x) { return fmt_encode(FMT_BF16, x); }
+double orc_from_f16(uint16_t h) { return fmt_decode(FMT_F16, h); }
+double orc_from_bf16(uint16_t h) { return fmt_decode(FMT_BF16, h); }
+
+static int is_half(int dtype) { return dtype == ORC_F16 || dtype == ORC_BF16; }
+static orc_fmt half_fmt(int dtype) { return dtype == ORC_F16 ? FMT_F16 : FMT_BF16; }
 
 /* Total order on doubles with -0 < +0 (no NaN in the inputs). */
 static int less_f64(double a, double b) {
@@ -113,6 +181,22 @@ static void apply_op(int dtype, int op, void *dst, const void *src) {
       else if (op == ORC_MAX) a = a < b ? b : a;
       else if (op == ORC_MIN) a = b < a ? b : a;
       *(int64_t *)dst = a;
+      break;
+    }
+    case ORC_F16:
+    case ORC_BF16: {
+      /* the exact sum / product (exact in binary64 for binary16; for
+       * bfloat16 binary64's 53 bits >= 2 x 8 + 2 make the rounding through
+       * binary64 equal to a single rounding) rounded once to the format */
+      const orc_fmt f = half_fmt(dtype);
+      const uint16_t ha = *(uint16_t *)dst, hb = *(const uint16_t *)src;
+      const double a = fmt_decode(f, ha), b = fmt_decode(f, hb);
+      uint16_t r = ha;
+      if (op == ORC_SUM) r = fmt_encode(f, a + b);
+      else if (op == ORC_PROD) r = fmt_encode(f, a * b);
+      else if (op == ORC_MAX) r = less_f64(a, b) ? hb : ha;
+      else if (op == ORC_MIN) r = less_f64(b, a) ? hb : ha;
+      *(uint16_t *)dst = r;
       break;
     }
     case ORC_PAIR: {
@@ -207,6 +291,17 @@ static float pwprod_f32(const float *x, int64_t n) {
   return pwprod_f32(x, m) * pwprod_f32(x + m, n - m);
 }
 
+/* The canonical pairwise tree (top-down) over n >= 1 elements of a 16-bit
+ * format, every node combined by apply_op (rounded to the format). */
+static uint16_t pw_half(int dtype, int op, const uint16_t *x, int64_t n) {
+  if (n == 1) return x[0];
+  int64_t m = largest_pow2_below(n);
+  uint16_t a = pw_half(dtype, op, x, m);
+  uint16_t b = pw_half(dtype, op, x + m, n - m);
+  apply_op(dtype, op, &a, &b);
+  return a;
+}
+
 double orc_pairwise_f64(const double *x, int64_t n, int form) {
   if (n < 1) return 0.0;
   return form == ORC_PW_BOTTOMUP ? pw_f64_bottomup(x, n) : pw_f64_topdown(x, n);
@@ -233,6 +328,12 @@ int orc_bcast(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int6
 }
 
 /* ----------------------------------------------------------------- Reduce */
+
+/* Floating-point SUM and PROD go through the pairwise tree; every other op
+ * folds in leaf order (its result does not depend on the order). */
+static int tree_op(int dtype, int op) {
+  return (op == ORC_SUM || op == ORC_PROD) && (dtype == ORC_F64 || dtype == ORC_F32 || is_half(dtype));
+}
 
 /* Leaf lists L_r in ascending leaf index, as a counting sort: start[r] is
  * the first position of root r in order[], order[] holds leaf indices. */
@@ -269,13 +370,16 @@ int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int
     const int64_t *Lr = order + start[r];
     for (int c = 0; c < bs; c++) {
       char *dst = root + r * us + c * es;
-      if ((op == ORC_SUM || op == ORC_PROD) && (dtype == ORC_F64 || dtype == ORC_F32)) {
+      if (tree_op(dtype, op)) {
         /* root op PW(leaves in ascending leaf index) */
         for (int64_t k = 0; k < deg; k++) {
           int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
           memcpy((char *)tmp + k * es, leaf + slot * us + c * es, (size_t)es);
         }
-        if (dtype == ORC_F64) {
+        if (is_half(dtype)) {
+          uint16_t t = pw_half(dtype, op, (const uint16_t *)tmp, deg);
+          apply_op(dtype, op, dst, &t);
+        } else if (dtype == ORC_F64) {
           if (op == ORC_SUM) {
             double t = orc_pairwise_f64((const double *)tmp, deg, pw_form);
             *(double *)dst = *(double *)dst + t;
@@ -312,7 +416,7 @@ int orc_reduce(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int
 int orc_fetch_and_op(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const int64_t *iroot,
                      int dtype, int bs, int op, void *rootdata, const void *leafdata, void *leafupdate) {
   if (check_graph(nroots, nleaves, ilocal, iroot, dtype, bs)) return -1;
-  if (dtype == ORC_PAIR || !(op == ORC_SUM || op == ORC_MAX || op == ORC_MIN)) return -1;
+  if (dtype == ORC_PAIR || is_half(dtype) || !(op == ORC_SUM || op == ORC_MAX || op == ORC_MIN)) return -1;
   int64_t es = elem_size(dtype), us = es * bs;
   char *root = (char *)rootdata;
   const char *leaf = (const char *)leafdata;

@@ -28,8 +28,12 @@ extern "C" {
 #endif
 
 /* Element types.  ORC_PAIR is the MAXLOC / MINLOC pair {double v; int32 i; int32 pad}
- * with a 16-byte extent; pad is never read or written. */
-enum { ORC_F64 = 0, ORC_F32 = 1, ORC_I32 = 2, ORC_I64 = 3, ORC_PAIR = 4 };
+ * with a 16-byte extent; pad is never read or written.  ORC_F16 (IEEE
+ * binary16) and ORC_BF16 (bfloat16: binary32's sign and exponent with 7
+ * fraction bits) are stored as their 16-bit patterns; every SUM, PROD of
+ * them is the exact result rounded once to the format (nearest, ties to
+ * even, overflow to infinity), MAX / MIN pick an operand. */
+enum { ORC_F64 = 0, ORC_F32 = 1, ORC_I32 = 2, ORC_I64 = 3, ORC_PAIR = 4, ORC_F16 = 5, ORC_BF16 = 6 };
 
 /* Operations (MPI_Op analogues, Section 3.2). */
 enum { ORC_REPLACE = 0, ORC_SUM = 1, ORC_MAX = 2, ORC_MIN = 3, ORC_MAXLOC = 4, ORC_MINLOC = 5, ORC_PROD = 6 };
@@ -90,6 +94,13 @@ int orc_csr_spmv_t(int64_t nrows, int64_t ncols, const int64_t *rowptr, const in
  *   m = the largest power of two strictly below n          (ORC_PW_TOPDOWN)
  * or, equivalently, repeated levels that add neighbours (2j, 2j+1) with an
  * unpaired last element passed up unchanged                 (ORC_PW_BOTTOMUP). */
+/* Round x to binary16 / bfloat16 (round to nearest, ties to even) and
+ * return the 16-bit pattern; decode a pattern.  Exposed for the pins. */
+uint16_t orc_to_f16(double x);
+uint16_t orc_to_bf16(double x);
+double orc_from_f16(uint16_t h);
+double orc_from_bf16(uint16_t h);
+
 double orc_pairwise_f64(const double *x, int64_t n, int form);
 float orc_pairwise_f32(const float *x, int64_t n, int form);
 

@@ -57,12 +57,15 @@ int orc_reduce_omp(int64_t nroots, int64_t nleaves, const int64_t *ilocal, const
       const int64_t *Lr = order + start[r];
       for (int c = 0; c < bs; c++) {
         char *dst = root + r * us + c * es;
-        if ((op == ORC_SUM || op == ORC_PROD) && (dtype == ORC_F64 || dtype == ORC_F32)) {
+        if (tree_op(dtype, op)) {
           for (int64_t k = 0; k < deg; k++) {
             int64_t slot = ilocal ? ilocal[Lr[k]] : Lr[k];
             memcpy((char *)tmp + k * es, leaf + slot * us + c * es, (size_t)es);
           }
-          if (dtype == ORC_F64) {
+          if (is_half(dtype)) {
+            uint16_t t = pw_half(dtype, op, (const uint16_t *)tmp, deg);
+            apply_op(dtype, op, dst, &t);
+          } else if (dtype == ORC_F64) {
             double t = op == ORC_SUM ? orc_pairwise_f64((const double *)tmp, deg, ORC_PW_TOPDOWN)
                                      : pwprod_f64((const double *)tmp, deg);
             *(double *)dst = op == ORC_SUM ? *(double *)dst + t : *(double *)dst * t;

@@ -245,6 +245,14 @@ def unit_data(rng, n, bs, dtype, kind="normal"):
     return rng.integers(-1000, 1000, size=shape, dtype=dtype)
 
 
+def bf16_bits(rng, n, bs=1, scale=1.0):
+    """bfloat16 data as 16-bit patterns (np.uint16): N(0, scale^2) binary32
+    values with the low 16 bits cleared, so every value is a bfloat16."""
+    shape = (n,) if bs == 1 else (n, bs)
+    x = (rng.standard_normal(shape) * scale).astype(np.float32)
+    return (x.view(np.uint32) >> 16).astype(np.uint16)
+
+
 def maxloc_leaves(rng, nleaves, ties=False):
     """MAXLOC leaf units: v ~ N(0,1) (quantised to 1/4 when ``ties``), i = leaf index."""
     a = np.zeros(nleaves, dtype=PAIR)

@@ -634,6 +634,152 @@ def test_omp_prod_minloc_equal_sequential(orc):
     assert np.array_equal(a["v"].view(np.uint64), b["v"].view(np.uint64)) and np.array_equal(a["i"], b["i"])
 
 
+# ---------------------------------------------- binary16 and bfloat16 units
+def test_f16_bf16_codecs_exhaustive(orc):
+    """Every 16-bit pattern decodes as NumPy's float16 / as the binary32 with
+    those high bits, and encodes back to itself (NaNs aside)."""
+    h = np.arange(65536, dtype=np.uint32).astype(np.uint16)
+    with np.errstate(invalid="ignore"):
+        f16 = h.view(np.float16).astype(np.float64)
+        bf = (h.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    for k in range(65536):
+        if not np.isnan(f16[k]):
+            d = orc.from_f16(int(h[k]))
+            assert d == f16[k] and np.signbit(d) == np.signbit(f16[k]), hex(k)
+            assert orc.to_f16(d) == k, hex(k)
+        if not np.isnan(bf[k]):
+            d = orc.from_bf16(int(h[k]))
+            assert d == bf[k] and np.signbit(d) == np.signbit(bf[k]), hex(k)
+            assert orc.to_bf16(d) == k, hex(k)
+
+
+def test_f16_bf16_rounding_against_libraries(orc):
+    """Rounding to binary16 equals NumPy's (correctly rounded from binary64);
+    rounding binary32 values to bfloat16 equals torch's (one rounding from
+    binary32); ties go to the even pattern; overflow gives infinity."""
+    import torch
+    rng = np.random.default_rng(60)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 6, 20000),
+                        rng.uniform(65000, 66000, 500), rng.uniform(0, 2 ** -14, 500)])
+    with np.errstate(over="ignore"):
+        want = x.astype(np.float16).view(np.uint16)
+    got = np.array([orc.to_f16(v) for v in x], np.uint16)
+    assert np.array_equal(got, want)
+    y = (rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000)).astype(np.float32)
+    want = torch.from_numpy(y).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    got = np.array([orc.to_bf16(float(v)) for v in y], np.uint16)
+    assert np.array_equal(got, want)
+    assert orc.to_f16(1 + 2 ** -11) == 0x3C00 and orc.to_f16(1 + 3 * 2 ** -11) == 0x3C02
+    assert orc.to_bf16(1 + 2 ** -8) == 0x3F80 and orc.to_bf16(1 + 3 * 2 ** -8) == 0x3F82
+    assert orc.to_f16(65520.0) == 0x7C00 and orc.to_f16(65519.99) == 0x7BFF
+    assert orc.to_bf16(-3.5e38) == 0xFF80
+
+
+def _h(vals, fmt):
+    if fmt == "f16":
+        return np.array(vals, np.float64).astype(np.float16)
+    import oracle
+    return np.array([oracle.to_bf16(v) for v in vals], np.uint16).view(oracle.BF16)
+
+
+def _v(a, fmt):
+    import oracle
+    if fmt == "f16":
+        return np.asarray(a).astype(np.float64)
+    return np.array([oracle.from_bf16(int(b)) for b in np.asarray(a).view(np.uint16).reshape(-1)])
+
+
+@pytest.mark.parametrize("fmt,t,ulp", [("f16", 2.0 ** -11, 2.0 ** -10), ("bf16", 2.0 ** -8, 2.0 ** -7)])
+def test_half_sum_tree_closed_form(orc, fmt, t, ulp):
+    """PW([1, t, ..., t]) for n = 2^k with t half an ulp of 1: the pair
+    (1, t) rounds to 1 (tie to even), the pairs (t, t) give 2t = ulp(1)
+    exactly, so PW = 1 + (n/2 - 1) ulp(1); a left fold gives 1.  Every node
+    rounds to the unit's format (a binary32 tree would not lose the t)."""
+    for n in (2, 4, 8, 16, 64):
+        leaf = _h([1.0] + [t] * (n - 1), fmt)
+        out = orc.reduce(1, [0] * n, None, leaf, _h([0.0], fmt), "sum")
+        assert _v(out, fmt)[0] == 1 + (n // 2 - 1) * ulp, n
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_half_ops_degree_two_elementwise(orc, fmt):
+    """Roots of one or two leaves: root + (l0 + l1), root * (l0 * l1) and the
+    max / min, each operation rounded to the format -- written out with NumPy
+    float16 (whose operations round each binary32 result once, exact for
+    binary16 by the 2p + 2 rule) or with the decoded values for bfloat16."""
+    import oracle
+    rng = np.random.default_rng(61)
+    nroots = 3000
+    iroot = np.concatenate([np.arange(nroots), np.arange(0, nroots, 2)])
+    L = iroot.size
+    if fmt == "f16":
+        leaf = rng.standard_normal(L).astype(np.float16)
+        root = rng.standard_normal(nroots).astype(np.float16)
+    else:
+        leaf = inputs.bf16_bits(rng, L).view(oracle.BF16)
+        root = inputs.bf16_bits(rng, nroots).view(oracle.BF16)
+    lv, rv = _v(leaf, fmt), _v(root, fmt)
+    rnd = (lambda x: np.float64(np.float16(x))) if fmt == "f16" else (lambda x: oracle.from_bf16(oracle.to_bf16(x)))
+    for op in ("sum", "prod", "max", "min"):
+        got = _v(orc.reduce(nroots, iroot, None, leaf, root, op), fmt)
+        for r in range(0, nroots, 7):
+            ls = lv[iroot == r]
+            if op in ("sum", "prod"):
+                f = (lambda a, b: a + b) if op == "sum" else (lambda a, b: a * b)
+                t = ls[0] if ls.size == 1 else rnd(f(ls[0], ls[1]))
+                want = rnd(f(rv[r], t))
+            else:
+                want = (max if op == "max" else min)([rv[r], *ls])
+            assert got[r] == want, (op, r)
+
+
+@pytest.mark.parametrize("n", [3, 64, 1000])
+def test_half_sum_error_bound(orc, n):
+    """|PW - exact| <= gamma_h sum|x| with u = 2^-11 (binary16), 2^-8
+    (bfloat16); h = ceil(log2 n) levels, plus one for the root's addition."""
+    import oracle
+    rng = np.random.default_rng(62 + n)
+    for fmt, u in (("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
+        if fmt == "f16":
+            x = rng.standard_normal(n).astype(np.float16)
+        else:
+            x = inputs.bf16_bits(rng, n).view(oracle.BF16)
+        xv = _v(x, fmt)
+        got = _v(orc.reduce(1, [0] * n, None, x, _h([0.0], fmt), "sum"), fmt)[0]
+        h = math.ceil(math.log2(n)) + 1
+        g = h * u / (1 - h * u)
+        assert abs(got - math.fsum(xv.tolist())) <= g * float(np.abs(xv).sum())
+
+
+@pytest.mark.parametrize("fmt,e", [("f16", 4), ("bf16", 50)])
+def test_half_prod_tree_closed_form(orc, fmt, e):
+    """As for binary64: [2^e, 2^e, 2^2e, 2^-2e] multiplies to 2^2e through the
+    tree; the running product overflows (2^4e is past binary16's 65504 at
+    e = 4, past bfloat16's range at e = 50)."""
+    leaves = _h([2.0 ** e, 2.0 ** e, 2.0 ** (2 * e), 2.0 ** (-2 * e)], fmt)
+    out = orc.reduce(1, [0, 0, 0, 0], None, leaves, _h([1.0], fmt), "prod")
+    assert _v(out, fmt)[0] == 2.0 ** (2 * e)
+    out = orc.reduce(1, [0, 0], None, _h([2.0 ** (2 * e)] * 2, fmt), _h([2.0 ** (-2 * e)], fmt), "prod")
+    assert np.isinf(_v(out, fmt)[0])
+
+
+def test_half_bcast_and_replace(orc):
+    """Bcast of binary16 units: REPLACE copies the patterns; SUM rounds
+    leaf + root once (NumPy float16)."""
+    g = inputs.single_sf(seed=63, nroots=500, nleaves=2000, leafspace=2500)
+    rng = np.random.default_rng(63)
+    root = rng.standard_normal((g.nroots, 3)).astype(np.float16)
+    leaf = rng.standard_normal((g.leafspace, 3)).astype(np.float16)
+    got = orc.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, "replace")
+    want = leaf.copy()
+    want[g.ilocal] = root[g.iroot]
+    assert got.tobytes() == want.tobytes()
+    got = orc.bcast(g.nroots, g.iroot, g.ilocal, root, leaf, "sum")
+    want = leaf.copy()
+    want[g.ilocal] = leaf[g.ilocal] + root[g.iroot]
+    assert got.tobytes() == want.tobytes()
+
+
 # ------------------------------------------------ multi-SF, Gather, Scatter
 def test_fig2_gather_scatter(orc):
     """Fig. 2's multi-SF, Gather and Scatter against the values derived by
