@@ -69,8 +69,22 @@ typedef enum {
 /* Element type of a unit.  SF_F64_I32 is the MAXLOC / MINLOC pair
  * struct { double v; int32_t i; int32_t pad; } with a 16-byte extent; pad
  * never affects a result and is never written in the caller's roots or leaves
- * (large SFs copy whole 16-byte leaf units, pad included, into scratch). */
-typedef enum { SF_F64 = 0, SF_F32 = 1, SF_I32 = 2, SF_I64 = 3, SF_F64_I32 = 4 } sf_dtype;
+ * (large SFs copy whole 16-byte leaf units, pad included, into scratch).
+ * SF_F16 is IEEE binary16, SF_BF16 bfloat16 (binary32's sign and exponent
+ * with 7 fraction bits), both 2 bytes: every SUM / PROD of them is the exact
+ * result rounded once to the unit's format (nearest, ties to even), MAX / MIN
+ * order -0 < +0.  They take the direct deterministic kernels in every reduce
+ * mode (no per-element 16-bit atomics), are not partitioned, and are not
+ * accepted by FetchAndOp or in a batch (SF_ERR_UNSUPPORTED). */
+typedef enum {
+  SF_F64 = 0,
+  SF_F32 = 1,
+  SF_I32 = 2,
+  SF_I64 = 3,
+  SF_F64_I32 = 4,
+  SF_F16 = 5,
+  SF_BF16 = 6
+} sf_dtype;
 
 /* A unit is bs contiguous elements of one dtype: the "unit" MPI datatype of
  * Section 3.2.  Ops act per element (MAXLOC / MINLOC: per pair). */
@@ -80,8 +94,9 @@ typedef struct {
 } sf_unit;
 
 /* Operation (MPI_Op of Section 3.2, which names the MPI reductions as the
- * ops of Bcast and Reduce).  SUM, MAX, MIN and PROD act on F64, F32, I32 and
- * I64 (integers wrap around); MAXLOC and MINLOC on F64_I32 pairs.  PROD and
+ * ops of Bcast and Reduce).  SUM, MAX, MIN and PROD act on F64, F32, I32,
+ * I64 (integers wrap around), F16 and BF16; MAXLOC and MINLOC on F64_I32
+ * pairs.  PROD and
  * MINLOC have no native device atomic: they combine through the
  * deterministic kernels in every reduce mode. */
 typedef enum { SF_REPLACE = 0, SF_SUM = 1, SF_MAX = 2, SF_MIN = 3, SF_MAXLOC = 4, SF_MINLOC = 5, SF_PROD = 6 } sf_op;

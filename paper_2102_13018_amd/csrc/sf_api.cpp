@@ -234,7 +234,8 @@ extern "C" int sf_fetch_and_op_begin(sf_t sf, sf_unit unit, void *rootdata, cons
   std::lock_guard<std::mutex> g(sf->mu);
   int rc = begin_common(sf, 2, unit, op, rootdata, leafdata, leafupdate);
   if (rc) return rc;
-  if (unit.dtype == SF_F64_I32 || op != SF_SUM) return SF_ERR_UNSUPPORTED;
+  if (unit.dtype == SF_F64_I32 || unit.dtype == SF_F16 || unit.dtype == SF_BF16 || op != SF_SUM)
+    return SF_ERR_UNSUPPORTED;
   if (sf->nleaves > 0 && leafupdate == leafdata) return SF_ERR_ARG;
   rc = launch_fetch_and_op(sf, unit, rootdata, leafdata, leafupdate, op, stream);
   if (rc) return rc;

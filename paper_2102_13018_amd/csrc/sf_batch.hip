@@ -521,7 +521,8 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
       return SF_ERR_ARG;
     }
     const int es = elem_size(it.unit.dtype);
-    if (es <= 0 || it.unit.bs < 1 || it.unit.dtype == SF_F64_I32 || es * (int64_t)it.unit.bs > 4096) {
+    if (es <= 0 || it.unit.bs < 1 || it.unit.dtype == SF_F64_I32 || it.unit.dtype == SF_F16 ||
+        it.unit.dtype == SF_BF16 || es * (int64_t)it.unit.bs > 4096) {
       delete b;
       return es <= 0 || it.unit.bs < 1 ? SF_ERR_ARG : SF_ERR_UNSUPPORTED;
     }

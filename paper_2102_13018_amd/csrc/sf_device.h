@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "sf_internal.h"
 
@@ -16,6 +17,33 @@ struct Pair {
   int32_t i;
   int32_t pad;
 };
+
+// binary16 and bfloat16 elements, held as their 16-bit patterns.  SUM and
+// PROD compute in binary32 and round once to the format (round to nearest,
+// ties to even): binary32's 24 bits are at least 2p + 2 for p = 11 and 8,
+// so the binary32 rounding never changes the final one and the result is
+// the exact one rounded once.  MAX / MIN compare 16-bit order keys.
+struct H16 {
+  uint16_t b;
+};
+struct BF16 {
+  uint16_t b;
+};
+template <typename T>
+constexpr bool kIsHalf = std::is_same<T, H16>::value || std::is_same<T, BF16>::value;
+
+__device__ __forceinline__ float to_f32(H16 h) { return (float)__builtin_bit_cast(_Float16, h.b); }
+__device__ __forceinline__ float to_f32(BF16 h) { return __uint_as_float((uint32_t)h.b << 16); }
+// binary32 -> binary16 by the hardware conversion (round to nearest even)
+__device__ __forceinline__ H16 from_f32(float x, H16) { return H16{__builtin_bit_cast(uint16_t, (_Float16)x)}; }
+// binary32 -> bfloat16: add half an ulp of the kept part, minus one when the
+// kept part is even, and truncate (round to nearest, ties to even; no NaN)
+__device__ __forceinline__ BF16 from_f32(float x, BF16) {
+  const uint32_t u = __float_as_uint(x);
+  return BF16{(uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};
+}
+// order key of a sign-magnitude 16-bit pattern: -0 < +0
+__device__ __forceinline__ uint32_t hkey(uint16_t b) { return b & 0x8000u ? (uint32_t)(uint16_t)~b : (uint32_t)b | 0x8000u; }
 
 // Total-order key of a float / double: unsigned compare of the key orders
 // the values with -0 < +0 (no NaN in the inputs).
@@ -110,6 +138,20 @@ struct Op<OP, uint32_t> {
     return b < a ? b : a;
   }
 };
+template <int OP, typename T>
+struct OpHalf {
+  static __device__ __forceinline__ T apply(T a, T b) {
+    if (OP == OP_SUM) return from_f32(to_f32(a) + to_f32(b), T{});
+    if (OP == OP_PROD) return from_f32(to_f32(a) * to_f32(b), T{});
+    if (OP == OP_MAX) return hkey(a.b) < hkey(b.b) ? b : a;
+    if (OP == OP_MIN) return hkey(b.b) < hkey(a.b) ? b : a;
+    return b;
+  }
+};
+template <int OP>
+struct Op<OP, H16> : OpHalf<OP, H16> {};
+template <int OP>
+struct Op<OP, BF16> : OpHalf<OP, BF16> {};
 template <int OP>
 struct Op<OP, Pair> {
   static __device__ __forceinline__ Pair apply(Pair a, Pair b) {
@@ -159,6 +201,8 @@ __device__ __forceinline__ Pair shfl_down(Pair v, int d) {
   r.pad = 0;
   return r;
 }
+__device__ __forceinline__ H16 shfl_down(H16 v, int d) { return H16{(uint16_t)__shfl_down((int)v.b, d)}; }
+__device__ __forceinline__ BF16 shfl_down(BF16 v, int d) { return BF16{(uint16_t)__shfl_down((int)v.b, d)}; }
 __device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return (uint32_t)__shfl_down((int)v, d); }
 __device__ __forceinline__ uint64_t shfl_down(uint64_t v, int d) {
   return (uint64_t)__shfl_down((long long)v, d);
@@ -175,9 +219,13 @@ __device__ __forceinline__ float shfl_idx(float v, int l) { return __shfl(v, l);
 // Streaming (non-temporal) accesses for data used once, so that it does not
 // displace reused lines from the caches.  Values of 4, 8 and 16 bytes go
 // through the native integer vector of that size (aligned to it in the
-// buffers they stream).
+// buffers they stream), 2-byte values as one short.
 template <int BYTES>
 struct NtBytes;
+template <>
+struct NtBytes<2> {
+  typedef unsigned short type;
+};
 template <>
 struct NtBytes<4> {
   typedef unsigned int type;

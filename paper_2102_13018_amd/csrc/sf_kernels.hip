@@ -629,8 +629,10 @@ int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, h
       bcast_move_w<uint4>(sf, (int)(ub / 16), root, leaf, st);
     else if (ub % 8 == 0 && a % 8 == 0)
       bcast_move_w<uint2>(sf, (int)(ub / 8), root, leaf, st);
-    else
+    else if (ub % 4 == 0 && a % 4 == 0)
       bcast_move_w<uint32_t>(sf, (int)(ub / 4), root, leaf, st);
+    else  // 16-bit units of an odd count
+      bcast_move_w<uint16_t>(sf, (int)(ub / 2), root, leaf, st);
     return check_launch();
   }
   int rc;
@@ -639,6 +641,8 @@ int launch_bcast(sf_s *sf, sf_unit unit, const void *root, void *leaf, int op, h
     case SF_F32: rc = bcast_op_t<float>(sf, unit.bs, op, root, leaf, st); break;
     case SF_I32: rc = bcast_op_t<int32_t>(sf, unit.bs, op, root, leaf, st); break;
     case SF_I64: rc = bcast_op_t<int64_t>(sf, unit.bs, op, root, leaf, st); break;
+    case SF_F16: rc = bcast_op_t<H16>(sf, unit.bs, op, root, leaf, st); break;
+    case SF_BF16: rc = bcast_op_t<BF16>(sf, unit.bs, op, root, leaf, st); break;
     case SF_F64_I32: {
       const DevPlan &d = sf->dp;
       const unsigned g = (unsigned)sf->hp.tiles.size();
@@ -679,8 +683,11 @@ static int reduce_det_t(sf_s *sf, const T *leaf, T *root, int bs, hipStream_t st
   const DevPlan &d = sf->dp;
   const HostPlan &h = sf->hp;
   const size_t ub = sizeof(T) * (size_t)bs;
-  if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)ub) >= 0 && scratch_fits(sf, part_scratch_need(sf, ub)))
-    return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
+  if constexpr (!kIsHalf<T>) {  // 16-bit units are not partitioned
+    if (OP != OP_REPLACE && h.part_red_det && stage_class((int64_t)ub) >= 0 &&
+        scratch_fits(sf, part_scratch_need(sf, ub)))
+      return launch_reduce_part<T, OP>(sf, leaf, root, bs, false, st);
+  }
   if (OP != OP_REPLACE && h.split && ub > kSplitMinUnit) return reduce_split_t<T, OP>(sf, leaf, root, bs, st);
   if (OP == OP_REPLACE) {
     const int64_t T_ = (int64_t)h.troot.size();
@@ -798,6 +805,29 @@ static int reduce_t(sf_s *sf, int op, int mode, const void *leafv, void *rootv, 
 #undef SF_RED
 }
 
+// 16-bit floating-point units: no per-element 16-bit atomics, so every
+// reduce mode takes the deterministic kernels.
+template <typename T>
+static int reduce_half_t(sf_s *sf, int op, const void *leafv, void *rootv, int bs, hipStream_t st) {
+  const T *leaf = (const T *)leafv;
+  T *root = (T *)rootv;
+  const bool dup = sf->has_dup_roots;
+#define SF_RED(OPV)                                                  \
+  do {                                                               \
+    if (!dup) return reduce_plain_t<T, OPV>(sf, leaf, root, bs, st); \
+    return reduce_det_t<T, OPV>(sf, leaf, root, bs, st);             \
+  } while (0)
+  switch (op) {
+    case SF_REPLACE: SF_RED(OP_REPLACE);
+    case SF_SUM: SF_RED(OP_SUM);
+    case SF_MAX: SF_RED(OP_MAX);
+    case SF_MIN: SF_RED(OP_MIN);
+    case SF_PROD: SF_RED(OP_PROD);
+    default: return SF_ERR_UNSUPPORTED;
+  }
+#undef SF_RED
+}
+
 int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, hipStream_t st) {
   if (sf->nleaves == 0) return SF_OK;
   if (op == SF_REPLACE && unit.dtype != SF_F64_I32 && sf->hp.all_contig && !sf->has_dup_roots)
@@ -808,6 +838,8 @@ int launch_reduce(sf_s *sf, sf_unit unit, const void *leaf, void *root, int op, 
     case SF_F32: return reduce_t<float>(sf, op, mode, leaf, root, unit.bs, st);
     case SF_I32: return reduce_t<int32_t>(sf, op, mode, leaf, root, unit.bs, st);
     case SF_I64: return reduce_t<int64_t>(sf, op, mode, leaf, root, unit.bs, st);
+    case SF_F16: return reduce_half_t<H16>(sf, op, leaf, root, unit.bs, st);
+    case SF_BF16: return reduce_half_t<BF16>(sf, op, leaf, root, unit.bs, st);
     case SF_F64_I32: {
       const Pair *l = (const Pair *)leaf;
       Pair *r = (Pair *)root;

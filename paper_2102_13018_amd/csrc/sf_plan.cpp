@@ -42,6 +42,8 @@ int elem_size(int32_t dtype) {
     case SF_I32: return 4;
     case SF_I64: return 8;
     case SF_F64_I32: return 16;
+    case SF_F16: return 2;
+    case SF_BF16: return 2;
     default: return 0;
   }
 }

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libsf.so")
 
 # enums of sf.h
-SF_F64, SF_F32, SF_I32, SF_I64, SF_F64_I32 = 0, 1, 2, 3, 4
+SF_F64, SF_F32, SF_I32, SF_I64, SF_F64_I32, SF_F16, SF_BF16 = 0, 1, 2, 3, 4, 5, 6
 SF_REPLACE, SF_SUM, SF_MAX, SF_MIN, SF_MAXLOC, SF_MINLOC, SF_PROD = 0, 1, 2, 3, 4, 5, 6
 SF_REDUCE_AUTO, SF_REDUCE_ATOMIC, SF_REDUCE_DETERMINISTIC = 0, 1, 2
 SF_COPY_VALUES, SF_USE_POINTER, SF_OWN_POINTER = 0, 1, 2
@@ -26,7 +26,7 @@ SF_NOALLOC_SCRATCH_BYTES = 64 << 20
 OPS = {"replace": SF_REPLACE, "sum": SF_SUM, "max": SF_MAX, "min": SF_MIN, "maxloc": SF_MAXLOC,
        "minloc": SF_MINLOC, "prod": SF_PROD}
 MODES = {"auto": SF_REDUCE_AUTO, "atomic": SF_REDUCE_ATOMIC, "deterministic": SF_REDUCE_DETERMINISTIC}
-ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16}
+ELEM_SIZE = {SF_F64: 8, SF_F32: 4, SF_I32: 4, SF_I64: 8, SF_F64_I32: 16, SF_F16: 2, SF_BF16: 2}
 
 EXPORTS = [
     "sf_create", "sf_setup", "sf_set_reduce_mode", "sf_bcast_begin", "sf_bcast_end",
@@ -164,7 +164,8 @@ def _ptr(x):
     return x.data_ptr()
 
 
-_UNIT_TORCH = {SF_F64: "torch.float64", SF_F32: "torch.float32", SF_I32: "torch.int32", SF_I64: "torch.int64"}
+_UNIT_TORCH = {SF_F64: "torch.float64", SF_F32: "torch.float32", SF_I32: "torch.int32", SF_I64: "torch.int64",
+               SF_F16: "torch.float16", SF_BF16: "torch.bfloat16"}
 
 
 def check_buffer(x, nunits, unit, what):
@@ -202,7 +203,7 @@ def unit_of(t, dtype=None, bs=None):
     import torch
     if dtype is None:
         dtype = {torch.float64: SF_F64, torch.float32: SF_F32, torch.int32: SF_I32,
-                 torch.int64: SF_I64}[t.dtype]
+                 torch.int64: SF_I64, torch.float16: SF_F16, torch.bfloat16: SF_BF16}[t.dtype]
     if bs is None:
         bs = 1 if t.dim() <= 1 else int(np.prod(t.shape[1:]))
     return SfUnit(dtype, bs)

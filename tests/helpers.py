@@ -7,14 +7,18 @@ import torch
 from paper_2102_13018_amd import sf as S
 
 PAIR = np.dtype([("v", "<f8"), ("i", "<i4"), ("pad", "<i4")])
+BF16 = np.dtype([("bf16", "<u2")])     # bfloat16 patterns (the oracle's carrier dtype)
 
 
 def sfdtype(a):
     a = np.asarray(a)
     if a.dtype == PAIR:
         return S.SF_F64_I32
+    if a.dtype == BF16:
+        return S.SF_BF16
     return {np.dtype(np.float64): S.SF_F64, np.dtype(np.float32): S.SF_F32,
-            np.dtype(np.int32): S.SF_I32, np.dtype(np.int64): S.SF_I64}[a.dtype]
+            np.dtype(np.int32): S.SF_I32, np.dtype(np.int64): S.SF_I64,
+            np.dtype(np.float16): S.SF_F16}[a.dtype]
 
 
 def unit(a):
