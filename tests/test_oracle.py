@@ -456,6 +456,32 @@ def test_multi_sf_permutation(orc):
     assert np.array_equal(r, root0 + deg)
 
 
+@pytest.mark.parametrize("op", ["max", "min"])
+@pytest.mark.parametrize("dtype", [np.float64, np.int32])
+def test_fetch_and_op_maxmin_running_extremes(orc, op, dtype):
+    """FetchAndOp MAX / MIN: each leaf fetches the extreme of its root's
+    start value and of the leaves before it in leaf order -- the running
+    extreme (np.maximum / np.minimum .accumulate) of [root0, leaves...]
+    shifted by one -- and the root ends at the extreme of all of them."""
+    rng = np.random.default_rng(70)
+    nroots, nleaves = 40, 2000
+    iroot = rng.integers(0, nroots, nleaves)
+    ilocal = rng.permutation(nleaves + 50)[:nleaves]
+    leaf = inputs.unit_data(rng, nleaves + 50, 1, dtype)
+    root = inputs.unit_data(rng, nroots, 1, dtype)
+    upd = np.zeros_like(leaf)
+    r_got, u_got = orc.fetch_and_op(nroots, iroot, ilocal, root, leaf, upd, op)
+    acc = np.maximum.accumulate if op == "max" else np.minimum.accumulate
+    want_u = upd.copy()
+    want_r = root.copy()
+    for r in range(nroots):
+        lv = np.nonzero(iroot == r)[0]                       # ascending leaf index
+        seq = acc(np.concatenate([root[r:r + 1], leaf[ilocal[lv]]]))
+        want_u[ilocal[lv]] = seq[:-1]
+        want_r[r] = seq[-1]
+    assert u_got.tobytes() == want_u.tobytes() and r_got.tobytes() == want_r.tobytes()
+
+
 # ------------------------------------------------ brute force, tiny graphs
 def brute_reduce_sum_exact(nroots, iroot, ilocal, leaf, root):
     out = [Fraction(float(v)) for v in root]
