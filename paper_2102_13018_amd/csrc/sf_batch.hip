@@ -135,17 +135,14 @@ __device__ __forceinline__ void bw_det_class(const BatchItemDev &it, const Batch
     const int t = cls[bt.t0 + kk];
     const int g0 = it.toff[t];
     const int n = it.toff[t + 1] - g0;
-    Vec<T, NV> x[D];
-#pragma unroll
-    for (int p = 0; p < D; p++)
-      if (p < n) x[p] = ld_stream(reinterpret_cast<const Vec<T, NV> *>(leaf + (int64_t)ld_stream(it.sl + g0 + p) * bs + c));
-#pragma unroll
-    for (int d = 1; d < D; d *= 2)
-#pragma unroll
-      for (int p = 0; p + d < D; p += 2 * d)
-        if (p + d < n) x[p] = vop<OP_SUM, T, NV>(x[p], x[p + d]);
+    const Vec<T, NV> v = pw_tree<D, Vec<T, NV>>(
+        n,
+        [&](int p) {
+          return ld_stream(reinterpret_cast<const Vec<T, NV> *>(leaf + (int64_t)ld_stream(it.sl + g0 + p) * bs + c));
+        },
+        [](const Vec<T, NV> &a, const Vec<T, NV> &b) { return vop<OP_SUM, T, NV>(a, b); });
     T *rp = root + (int64_t)it.troot[t] * bs + c;
-    vst<T, NV>(rp, vop<OP_SUM, T, NV>(vld<T, NV>(rp), x[0]));
+    vst<T, NV>(rp, vop<OP_SUM, T, NV>(vld<T, NV>(rp), v));
   }
 }
 
@@ -257,22 +254,31 @@ __device__ __forceinline__ void bw_fop_det_class(const BatchItemDev &it, const B
     const int t = cls[bt.t0 + kk];
     const int g0 = it.toff[t];
     const int n = it.toff[t + 1] - g0;
-    int64_t sl[D];
-    T x[D];
-#pragma unroll
-    for (int p = 0; p < D; p++)
-      if (p < n) sl[p] = (int64_t)ld_stream(it.sl + g0 + p) * bs + c;
-#pragma unroll
-    for (int p = 0; p < D; p++)
-      if (p < n) x[p] = ld_stream(leaf + sl[p]);
     T *rp = root + (int64_t)it.troot[t] * bs + c;
     T acc = *rp;
+    // blocks of 8 leaves, one at a time (registers for 8 slots and values)
+    constexpr int B = D < 8 ? D : 8;
 #pragma unroll
-    for (int p = 0; p < D; p++)
-      if (p < n) {
-        st_stream(upd + sl[p], acc);
-        acc = Op<OP_SUM, T>::apply(acc, x[p]);
+    for (int k = 0; k < D / B; k++) {
+      const int m = n - k * B;
+      if (m > 0) {
+        int64_t sl[B];
+        T x[B];
+#pragma unroll
+        for (int p = 0; p < B; p++)
+          if (p < m) sl[p] = (int64_t)ld_stream(it.sl + g0 + k * B + p) * bs + c;
+#pragma unroll
+        for (int p = 0; p < B; p++)
+          if (p < m) x[p] = ld_stream(leaf + sl[p]);
+#pragma unroll
+        for (int p = 0; p < B; p++)
+          if (p < m) {
+            st_stream(upd + sl[p], acc);
+            acc = Op<OP_SUM, T>::apply(acc, x[p]);
+          }
       }
+      if constexpr (D > B) __builtin_amdgcn_sched_barrier(0);
+    }
     *rp = acc;
   }
 }

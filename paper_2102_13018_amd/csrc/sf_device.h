@@ -524,6 +524,44 @@ __device__ __forceinline__ Vec<T, NV> vop(const Vec<T, NV> &a, const Vec<T, NV> 
   for (int i = 0; i < NV; i++) r.x[i] = Op<OP, T>::apply(a.x[i], b.x[i]);
   return r;
 }
+// The canonical pairwise tree (bottom-up form) of the n <= D values load(p),
+// p = 0 .. n-1, combined by comb.  At most 8 values are live at once: a
+// block of 8 consecutive positions is reduced by the levels at distance 1,
+// 2 and 4 (whose pairs never leave the block), and the block results are
+// combined at distances 8, 16, ... -- the same operands in the same order as
+// the tree over all D positions, with a fraction of its registers (which
+// keeps kernels with a 32-leaf class at a useful occupancy).
+template <int D, typename V, typename Load, typename Comb>
+__device__ __forceinline__ V pw_tree(int n, Load load, Comb comb) {
+  constexpr int BMAX = sizeof(V) >= 16 ? 4 : 8;
+  constexpr int B = D < BMAX ? D : BMAX;
+  constexpr int NB = D / B;
+  V blk[NB];
+#pragma unroll
+  for (int k = 0; k < NB; k++) {
+    const int m = n - k * B;
+    if (m > 0) {
+      V x[B];
+#pragma unroll
+      for (int p = 0; p < B; p++)
+        if (p < m) x[p] = load(k * B + p);
+#pragma unroll
+      for (int d = 1; d < B; d *= 2)
+#pragma unroll
+        for (int p = 0; p + d < B; p += 2 * d)
+          if (p + d < m) x[p] = comb(x[p], x[p + d]);
+      blk[k] = x[0];
+    }
+    if constexpr (NB > 1) __builtin_amdgcn_sched_barrier(0);  // one block's loads live at a time
+  }
+#pragma unroll
+  for (int d = 1; d < NB; d *= 2)
+#pragma unroll
+    for (int p = 0; p + d < NB; p += 2 * d)
+      if ((p + d) * B < n) blk[p] = comb(blk[p], blk[p + d]);
+  return blk[0];
+}
+
 template <typename T, int NV>
 __device__ __forceinline__ Vec<T, NV> vld(const T *p) {
   if constexpr (NV == 1) {

@@ -237,16 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_maxloc_stream(const DevSegment *__re
 template <typename T, int OP, int NV, int D>
 __device__ __forceinline__ Vec<T, NV> small_tree_v(const int32_t *__restrict__ sl, const T *__restrict__ leaf, int g0,
                                                    int n, int bs, int c) {
-  Vec<T, NV> x[D];
-#pragma unroll
-  for (int p = 0; p < D; p++)
-    if (p < n) x[p] = vld<T, NV>(leaf + (int64_t)sl[g0 + p] * bs + c);
-#pragma unroll
-  for (int d = 1; d < D; d *= 2)
-#pragma unroll
-    for (int p = 0; p + d < D; p += 2 * d)
-      if (p + d < n) x[p] = vop<OP, T, NV>(x[p], x[p + d]);
-  return x[0];
+  return pw_tree<D, Vec<T, NV>>(
+      n, [&](int p) { return vld<T, NV>(leaf + (int64_t)sl[g0 + p] * bs + c); },
+      [](const Vec<T, NV> &a, const Vec<T, NV> &b) { return vop<OP, T, NV>(a, b); });
 }
 
 template <typename T, int OP, int NV>
