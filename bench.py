@@ -177,16 +177,37 @@ def build_spmv_ops(torch, S, inputs, g):
     return sf, ops, direct, data
 
 
+class CacheFlush:
+    """Evicts an op's data from the L2s and the 256 MB Infinity Cache before
+    it runs.  kind "read" reads a 1 GiB buffer (a reduction): the caches then
+    hold clean lines of that buffer and none of the op's data.  kind "write"
+    overwrites the buffer instead, which also leaves up to 256 MB of dirty
+    lines that the op pays to write back -- time that belongs to the flush,
+    reported beside the headline."""
+
+    def __init__(self, torch, kind="read"):
+        self.torch, self.kind = torch, kind
+        self.buf = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        self.buf.fill_(1.0)
+        self.acc = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        if self.kind == "read":
+            self.torch.sum(self.buf, dim=0, out=self.acc)
+        else:
+            self.buf.fill_(1.0)
+
+
 def time_ops(torch, ops, steps, warmup, flush=None):
     """Warm up, then time exactly `steps` steps; every op is bracketed by
     events on the current stream (the stream the library launches on).  With
-    `flush` (a >= 1 GiB device buffer), the buffer is overwritten before
-    every op, outside its events: L2 and the 256 MB Infinity Cache hold none
-    of the op's data when it starts (cold)."""
+    `flush` (a CacheFlush), the caches are flushed before every op, outside
+    its events: L2 and the Infinity Cache hold none of the op's data when it
+    starts (cold)."""
     for _ in range(warmup):
         for op in ops:
             if flush is not None:
-                flush.fill_(1.0)
+                flush()
             op.fn()
     torch.cuda.synchronize()
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
@@ -195,7 +216,7 @@ def time_ops(torch, ops, steps, warmup, flush=None):
     for s in range(steps):
         for k, op in enumerate(ops):
             if flush is not None:
-                flush.fill_(1.0)
+                flush()
             ev[s][k][0].record()
             op.fn()
             ev[s][k][1].record()
@@ -205,6 +226,20 @@ def time_ops(torch, ops, steps, warmup, flush=None):
         for k, op in enumerate(ops):
             op.times.append(ev[s][k][0].elapsed_time(ev[s][k][1]))
     return wall
+
+
+def cold_write_flush(torch, ops, steps, warmup, step_bytes):
+    """The step with a 1 GiB write before every op: the op also writes back
+    the flush's dirty lines that the Infinity Cache still holds."""
+    for o in ops:
+        o.times = []
+    fl = CacheFlush(torch, "write")
+    time_ops(torch, ops, steps, warmup, flush=fl)
+    del fl
+    dev_ms = float(np.mean([sum(o.times[s] for o in ops) for s in range(steps)]))
+    return {"cache": "cold, flushed by a 1 GiB write (dirty lines left in the Infinity Cache)",
+            "value": round(step_bytes / dev_ms / 1e6, 1), "ms_per_step": round(dev_ms, 3),
+            "ops": {o.name: round(float(np.median(o.times)) * 1e3, 1) for o in ops}}
 
 
 def warm_ops(torch, ops, steps, warmup):
@@ -506,7 +541,7 @@ def knn_row(torch, S, g, steps, flush, copy_gbps):
                        "frac_copy_ceiling": round(ach / copy_gbps, 4) if copy_gbps else None,
                        "kernel": o.kernels, "traffic": measured_traffic(o.name)}
     return {"workload": f"knn(npoints={g.nroots}, k=8) fp32 x16 (64-byte units), each op alone",
-            "cache": "cold (1 GiB write before every op)", "ops": out}
+            "cache": "cold (1 GiB read before every op)", "ops": out}
 
 
 def spmv_row(torch, S, inputs, steps):
@@ -636,8 +671,8 @@ def main():
         return
 
     # the step, cold: the 256 MB Infinity Cache and the L2s are flushed by a
-    # 1 GiB write before every op (outside the op's events)
-    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    # 1 GiB read before every op (outside the op's events)
+    flush = CacheFlush(torch, "read")
     torch.cuda.synchronize()
     wall = time_ops(torch, ops, args.steps, args.warmup, flush=flush)
     step_bytes = sum(o.nbytes for o in ops)
@@ -668,9 +703,9 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "spmv_ghost(nroots=2000000, nleaves=16000000, zipf=1.1, 64 segments, seed=3)",
                       "ops_per_step": [o.name for o in ops], "step_alg_bytes": step_bytes,
-                      "cache": "cold: a 1 GiB write flushes L2 and the Infinity Cache before every op; "
+                      "cache": "cold: a 1 GiB read flushes L2 and the Infinity Cache before every op; "
                                "ms_per_step sums the ops' event times, the flushes lie outside them "
-                               "(warm numbers: ops_warm)",
+                               "(warm numbers: ops_warm; after a 1 GiB write instead: ops_cold_write_flush)",
                       "wall_ms_per_step_with_flushes": round(wall * 1e3 / args.steps, 3),
                       "setup_s": round(data["setup_s"], 2), "parallelism": "single-gpu"},
            "ops": per_op, "roofline": roofline, "copy_ceiling_GBps": copy_gbps,
@@ -680,6 +715,7 @@ def main():
         # step's kernels only): the warm step, the direct atomic kernels, and
         # the small / halo / batch / k-NN / autograd rows
         out["ops_warm"] = warm_ops(torch, ops, args.steps, args.warmup)
+        out["ops_cold_write_flush"] = cold_write_flush(torch, ops, args.steps, args.warmup, step_bytes)
         time_ops(torch, direct, max(5, args.steps // 2), 2)
         direct_row = {}
         for o in direct:
