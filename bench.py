@@ -78,6 +78,61 @@ def measured_traffic(op):
     return int(ops[op]["fetch_bytes"] + ops[op]["write_bytes"])
 
 
+def _dispatches(path):
+    """(kernel name, counter value) per dispatch of a rocprofv3 counter CSV,
+    in dispatch order."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            acc.setdefault(d, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+    return [tuple(acc[d]) for d in sorted(acc)]
+
+
+def _op_launches(disp, launches):
+    """The dispatches of the op: the library's (sfi::) dispatches at the end of
+    the run form `launches` identical launches; returns one launch's kernels
+    (name, total counter value over the launches)."""
+    lib = [d for d in disp if "sfi::" in d[0]]
+    for per in range(1, len(lib) // launches + 1):
+        tail = lib[len(lib) - per * launches:]
+        names = [n for n, _ in tail]
+        if all(names[i] == names[i % per] for i in range(len(names))):
+            out = {}
+            for n, v in tail:
+                out[n] = out.get(n, 0.0) + v
+            return out
+    raise ValueError("no repeated launch pattern in the counter dispatches")
+
+
+def pmc_summary(pmc_dir, launches, copy_bytes):
+    """profiles/hbm_traffic.json and profiles/spmv_ghost_hbm_counters.md from
+    rocprofv3 counter runs laid out as <pmc_dir>/<op>/<FETCH_SIZE|WRITE_SIZE>/
+    pmc_counter_collection.csv (one `--profile-op <op>` run per counter).
+    FETCH_SIZE and WRITE_SIZE are read in KiB and scaled by what they count
+    for the run's largest plain device copy of copy_bytes."""
+    ops, scale = {}, {}
+    for op in sorted(os.listdir(pmc_dir)):
+        vals = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            path = os.path.join(pmc_dir, op, ctr, "pmc_counter_collection.csv")
+            disp = _dispatches(path)
+            copy = max(v for n, v in disp if "copyBuffer" in n)
+            f = copy_bytes / (copy * 1024.0)
+            per = {n: v * 1024.0 * f / launches for n, v in _op_launches(disp, launches).items()}
+            vals[ctr] = (per, f)
+        kernels = {n: {"fetch_bytes": vals["FETCH_SIZE"][0][n], "write_bytes": vals["WRITE_SIZE"][0].get(n, 0.0)}
+                   for n in vals["FETCH_SIZE"][0]}
+        ops[op] = {"fetch_bytes": sum(k["fetch_bytes"] for k in kernels.values()),
+                   "write_bytes": sum(k["write_bytes"] for k in kernels.values()), "kernels": kernels}
+        scale[op] = {"fetch": vals["FETCH_SIZE"][1], "write": vals["WRITE_SIZE"][1]}
+    d = {"_device_code_hash": device_code_hash(), "_scale": scale, "ops": ops}
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -91,6 +146,10 @@ def parse():
                    help="run one row alone (for a profiler) and print its JSON")
     p.add_argument("--profile-op", default=None, help="comma-separated ops to run alone (steps times), for a profiler")
     p.add_argument("--copy-bytes", type=int, default=0, help="run a plain device copy of this size (counter scale)")
+    p.add_argument("--pmc-summary", default=None,
+                   help="write profiles/hbm_traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs in this "
+                        "directory (<op>/<counter>/pmc_counter_collection.csv; --steps + --warmup launches per op, "
+                        "--copy-bytes the copy that scales the counters); needs no GPU")
     p.add_argument("--partition-sweep", action="store_true",
                    help="time Reduce SUM f64 and FetchAndOp SUM int64 with partitioning off / on / auto on "
                         "Zipf and uniform SFs of 2^16..2^22 leaves (the automatic threshold's evidence)")
@@ -623,6 +682,11 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_summary:
+        d = pmc_summary(args.pmc_summary, args.steps + args.warmup, args.copy_bytes)
+        for op, v in d["ops"].items():
+            log(f"{op:32s} fetch {v['fetch_bytes'] / 1e6:8.1f} MB  write {v['write_bytes'] / 1e6:8.1f} MB")
+        return
     import torch
     from paper_2102_13018_amd import inputs
     from paper_2102_13018_amd import sf as S
