@@ -386,7 +386,7 @@ typedef struct {
 } sf_batch_item;
 
 /* Batch many independent SF operations (uneven sizes, units and kinds) so
- * that they run in ONE persistent kernel launch (Section 5.4: launch costs
+ * that they run in ONE kernel launch (Section 5.4: launch costs
  * that small kernels cannot hide).  The work table is built once here; the
  * buffers of the items are bound to the batch (the same pointers are used by
  * every launch).  The items' SFs must stay alive while the batch exists and
@@ -407,7 +407,7 @@ int sf_batch_launch(sf_batch_t batch, hipStream_t stream);
 /* Run the items one kernel launch per item (the per-SF comparison). */
 int sf_batch_launch_separate(sf_batch_t batch, hipStream_t stream);
 
-/* Capture the batch's launch sequence (mode 0: the single persistent
+/* Capture the batch's launch sequence (mode 0: the single batch
  * launch, mode 1: one launch per item) into a HIP graph on stream; later
  * sf_batch_graph_launch calls replay it.  Scratch memory the items need is
  * allocated before the capture.  sf_batch_set_config and sf_batch_autotune
@@ -416,7 +416,7 @@ int sf_batch_graph_capture(sf_batch_t batch, int32_t mode, hipStream_t stream);
 int sf_batch_graph_launch(sf_batch_t batch, hipStream_t stream);
 
 /* Time the candidate launch shapes (leaves per thread x tile size) of the
- * persistent kernel on stream and keep the fastest.  cache_path (may be
+ * batch kernel on stream and keep the fastest.  cache_path (may be
  * NULL) names a text file of earlier choices keyed by the batch's shape: a
  * hit skips the timing, a miss appends the result.  The candidates are
  * bit-identical in every result that is deterministic.  Launches the batch

@@ -1,12 +1,16 @@
-// sf_batch.hip -- many star-forest operations in ONE persistent launch.
+// sf_batch.hip -- many star-forest operations in ONE kernel launch.
 //
 // Section 5.4 of the paper shows why this matters: each kernel launch costs
 // microseconds, comparable to or larger than the work of one small pack or
 // unpack, and a host synchronisation between launches exposes that cost.
 // Here a batch of independent SF operations (uneven sizes, units and kinds)
-// becomes one table of equal-sized work tiles that a persistent grid walks
-// round-robin; the whole launch sequence can be captured into a HIP graph,
-// and an autotuner picks leaves per thread and tile size by timing.
+// becomes one table of equal-sized work tiles, longest first, and one launch
+// gives every tile a block of its own: the hardware dispatcher then balances
+// tiles of uneven cost across the CUs (measured faster than persistent grids
+// of 2048 or 4096 blocks walking the table, and far faster than blocks that
+// take tiles from a device counter, which serialises on one address).  The
+// launch can be captured into a HIP graph, and an autotuner picks leaves per
+// thread and tile size by timing.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -355,6 +359,7 @@ __device__ __forceinline__ void bw_reduce(const BatchItemDev &it, const BatchTil
   }
 }
 
+// One block per tile (a grid smaller than the table walks it in strides).
 template <int LPT>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev *__restrict__ items,
                                                   const BatchTile *__restrict__ tiles, int ntiles) {
@@ -469,7 +474,7 @@ static int batch_build_tiles(sf_batch_s *b) {
     for (int t0 = 0; t0 < nl; t0 += per)
       b->htiles.push_back({(int32_t)k, BW_RED_WAVE, 0, t0, std::min(nl, t0 + per), 0, 0, 0});
   }
-  // longest work first across items: round-robin then spreads it evenly
+  // longest work first across items: the dispatcher starts it first
   std::stable_sort(b->htiles.begin(), b->htiles.end(), [](const BatchTile &x, const BatchTile &y) {
     return (x.t1 - x.t0) > (y.t1 - y.t0);
   });
@@ -606,7 +611,7 @@ extern "C" int sf_batch_create(int32_t n, const sf_batch_item *items, sf_batch_t
 static int batch_launch_lpt(sf_batch_s *b, hipStream_t st) {
   const int nt = (int)b->htiles.size();
   if (nt == 0) return SF_OK;
-  const unsigned g = (unsigned)std::min(nt, kPersistBlocks);
+  const unsigned g = (unsigned)nt;  // a block per tile
   switch (b->lpt) {
     case 1: hipLaunchKernelGGL((k_batch<1>), dim3(g), dim3(kBlock), 0, st, b->ditems, b->dtiles, nt); break;
     case 2: hipLaunchKernelGGL((k_batch<2>), dim3(g), dim3(kBlock), 0, st, b->ditems, b->dtiles, nt); break;
@@ -740,7 +745,7 @@ extern "C" int sf_batch_autotune(sf_batch_t b, const char *cache_path, hipStream
     }
   }
   const int lpts[] = {1, 2, 4, 8};
-  const int tiles[] = {1024, 2048, 4096, 8192};
+  const int tiles[] = {256, 512, 1024, 2048, 4096};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SF_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -27,7 +27,6 @@ constexpr int kHotMinDeg = 64;       // smallest degree of such a candidate
 constexpr int kHotLdsBytes = 32768;  // LDS budget for the accumulators, default
 constexpr int kReduceGrid = 512;     // grid of the persistent atomic Reduce (measured best)
 constexpr int kFetchGrid = 1024;     // grid of the persistent atomic FetchAndOp (measured best)
-constexpr int kPersistBlocks = 2048; // grid of the persistent batch kernel
 constexpr size_t kMaxPending = 64;   // pending begin/end pairs reserved per SF
 constexpr size_t kSplitMinUnit = 8;  // the Reduce split is taken for larger units only (measured)
 // Partitioned deterministic path for large SFs (two fully coalesced passes
