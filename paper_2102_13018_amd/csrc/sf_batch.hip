@@ -462,10 +462,11 @@ static int batch_build_tiles(sf_batch_s *b) {
       continue;
     }
     // deterministic: tiles of roots per degree class, sized so that a tile
-    // carries about b->tile leaves
+    // carries about a quarter of b->tile leaves (their random gathers want
+    // more, smaller blocks than the streams: measured best at a quarter)
     for (int c = 0; c < kNumClasses; c++) {
       const int n = (int)sf->hp.cls[c].size();
-      const int per = std::max(1, b->tile >> c);
+      const int per = std::max(1, (b->tile / 4) >> c);
       for (int t0 = 0; t0 < n; t0 += per)
         b->htiles.push_back({(int32_t)k, BW_RED_DET, 0, t0, std::min(n, t0 + per), c, 0, 0});
     }
@@ -474,10 +475,28 @@ static int batch_build_tiles(sf_batch_s *b) {
     for (int t0 = 0; t0 < nl; t0 += per)
       b->htiles.push_back({(int32_t)k, BW_RED_WAVE, 0, t0, std::min(nl, t0 + per), 0, 0, 0});
   }
-  // longest work first across items: the dispatcher starts it first
-  std::stable_sort(b->htiles.begin(), b->htiles.end(), [](const BatchTile &x, const BatchTile &y) {
-    return (x.t1 - x.t0) > (y.t1 - y.t0);
-  });
+  // largest work first across items (the dispatcher starts it first), by
+  // the bytes a tile moves: its leaves x unit bytes, a degree-class-c tile of
+  // roots counting 2^c leaves per root and a wavefront tile kChunk per root
+  {
+    std::vector<int64_t> w(b->htiles.size());
+    for (size_t i = 0; i < w.size(); i++) {
+      const BatchTile &t = b->htiles[i];
+      const sf_batch_item &it = b->items[t.item];
+      int64_t n = t.t1 - t.t0;
+      if (t.work == BW_RED_DET || t.work == BW_FOP_DET)
+        n <<= t.cls;
+      else if (t.work == BW_RED_WAVE || t.work == BW_FOP_WAVE)
+        n *= kChunk;
+      w[i] = n * elem_size(it.unit.dtype) * it.unit.bs;
+    }
+    std::vector<size_t> ord(w.size());
+    for (size_t i = 0; i < ord.size(); i++) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return w[x] > w[y]; });
+    std::vector<BatchTile> sorted(ord.size());
+    for (size_t i = 0; i < ord.size(); i++) sorted[i] = b->htiles[ord[i]];
+    b->htiles.swap(sorted);
+  }
   const size_t bytes = std::max<size_t>(b->htiles.size(), 1) * sizeof(BatchTile);
   if (bytes > b->dtiles_cap) {
     if (b->dtiles) (void)hipFree(b->dtiles);  // a new, larger table replaces it
