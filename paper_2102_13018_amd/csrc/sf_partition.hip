@@ -85,6 +85,21 @@ struct MoveFix {
   const void *rbase;
 };
 
+// The 12 bytes of a (value, index) pair that a reduction reads: the
+// window-major scratch of the pair ops holds these instead of whole 16-byte
+// units, a quarter less written by pass A and read by pass B.
+struct alignas(4) P12 {
+  uint32_t x, y, z;
+};
+__device__ __forceinline__ P12 pair12(uint4 u) { return P12{u.x, u.y, u.z}; }
+__device__ __forceinline__ Pair unpair12(P12 v) {
+  Pair r;
+  r.v = __longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x));
+  r.i = (int32_t)v.z;
+  r.pad = 0;
+  return r;
+}
+
 #define SP_MOVE_ARGS                                                                                      \
   const uint16_t *__restrict__ pa_loc, const int32_t *__restrict__ pa_run0, const int32_t *__restrict__ pa_run, \
       const int32_t *__restrict__ tile_leaf0, const int32_t *__restrict__ pa_slot, int64_t L, int ta,           \
@@ -94,8 +109,11 @@ struct MoveFix {
 // roots (0x4000 alone in pa_loc) are not moved: pass A combines them per
 // group (HOT_TOTALS, HOT_PREFIX), pass C writes their fetched values
 // (HOT_APPLY).
-template <typename Word, int DIR, int P, int FIX, typename HS>
+// PAIR12 (pass A of the pair ops, Word uint4): scratch holds 12-byte P12
+// units (one per Word).
+template <typename Word, int DIR, int P, int FIX, typename HS, bool PAIR12>
 __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
+  static_assert(!PAIR12 || (DIR == 0 && FIX == 0 && std::is_same<Word, uint4>::value), "pair scratch: pass A");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t grp[kMoveGroups];
   Word *lds = reinterpret_cast<Word *>(smem);
@@ -213,7 +231,10 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
     if (leaf0 >= 0) {
       for (int c = 0; c < W; c++) {
         if (DIR == 0) {
-          scratch[s + c] = lds[src * W + c];
+          if constexpr (PAIR12)
+            reinterpret_cast<P12 *>(scratch)[s + c] = pair12(lds[src * W + c]);
+          else
+            scratch[s + c] = lds[src * W + c];
         } else {
           Word v = scratch[s + c];
           if constexpr (FIX != 0)
@@ -225,7 +246,10 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
       const int64_t l = (int64_t)pa_slot[p0 + src] * W;
       for (int c = 0; c < W; c++) {
         if (DIR == 0) {
-          scratch[s + c] = leaf[l + c];
+          if constexpr (PAIR12)
+            reinterpret_cast<P12 *>(scratch)[s + c] = pair12(leaf[l + c]);
+          else
+            scratch[s + c] = leaf[l + c];
         } else {
           Word v = scratch[s + c];
           if constexpr (FIX != 0)
@@ -251,15 +275,15 @@ __device__ __forceinline__ void sp_move_body(SP_MOVE_ARGS) {
 
 // Tiles of units up to 8 bytes take 64 KB of LDS; two blocks share a CU
 // when the kernel also stays within 64 VGPRs (8 waves per SIMD).
-template <typename Word, int DIR, int P, int FIX, typename HS>
+template <typename Word, int DIR, int P, int FIX, typename HS, bool PAIR12 = false>
 __global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sp_move2(SP_MOVE_ARGS) {
-  sp_move_body<Word, DIR, P, FIX, HS>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
-                                      run_cap, fx, ha, bs);
+  sp_move_body<Word, DIR, P, FIX, HS, PAIR12>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W,
+                                              run_off, run_cap, fx, ha, bs);
 }
-template <typename Word, int DIR, int P, int FIX, typename HS>
+template <typename Word, int DIR, int P, int FIX, typename HS, bool PAIR12 = false>
 __global__ __launch_bounds__(kStageThreads) void k_sp_move(SP_MOVE_ARGS) {
-  sp_move_body<Word, DIR, P, FIX, HS>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W, run_off,
-                                      run_cap, fx, ha, bs);
+  sp_move_body<Word, DIR, P, FIX, HS, PAIR12>(pa_loc, pa_run0, pa_run, tile_leaf0, pa_slot, L, ta, leaf, scratch, W,
+                                              run_off, run_cap, fx, ha, bs);
 }
 #undef SP_MOVE_ARGS
 
@@ -407,6 +431,17 @@ __device__ __forceinline__ auto lds_value(V v) {
   else
     return v;
 }
+// A window of pairs from their 12-byte scratch units.
+__device__ __forceinline__ void win_load_pair12(Pair *lds, const P12 *__restrict__ scr, const uint16_t *__restrict__ lpos,
+                                                const DevSWin &w, int bs) {
+  const P12 *src = scr + (int64_t)w.base * bs;
+  const int items = w.n * bs;
+#pragma unroll 4
+  for (int q = threadIdx.x; q < items; q += kStageThreads) {
+    const int k = bs == 1 ? q : q / bs;
+    lds[(int)(lpos[w.base + k] & 0x3fff) * bs + (q - k * bs)] = unpair12(src[q]);
+  }
+}
 template <typename T, typename V>
 __device__ __forceinline__ void win_load_key(V *lds, const T *__restrict__ scr, const uint16_t *__restrict__ lpos,
                                              const DevSWin &w, int bs) {
@@ -513,6 +548,8 @@ __device__ __forceinline__ void sp_reduce_body(const DevSWin *__restrict__ wins,
   for (int j = threadIdx.x; j < nb; j += kStageThreads) cd[j] = wchunk[win.big0 + j];
   if constexpr (K::on)
     win_load_key(lds, scr, lpos, win, bs);
+  else if constexpr (std::is_same<T, Pair>::value)
+    win_load_pair12(lds, reinterpret_cast<const P12 *>(scr), lpos, win, bs);
   else
     win_load(lds, scr, lpos, win, bs);
   __syncthreads();
@@ -916,7 +953,7 @@ int stage_class(int64_t unit_bytes) { return unit_bytes <= 8 ? 0 : (unit_bytes <
 // Move whole units between the leaf buffer and scratch (pass A / pass C),
 // with the hot-root phase HS when the plan has hot roots and the op takes
 // them (ha, bs: its arguments).
-template <typename Word, int DIR, int P, int FIX, typename HS>
+template <typename Word, int DIR, int P, int FIX, typename HS, bool PAIR12>
 static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx,
                      const HotArgs &ha, int bs) {
   const HostPlan::Stage &hs = sf->hp.sp[cls];
@@ -932,28 +969,28 @@ static int sp_move_p(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStr
   // 64-VGPR build), else in all of it; otherwise they are read from memory.
   if (tile + runs + hot_static <= kMoveLdsTwo) {
     const size_t lds = tile + runs;
-    int rc = allow_lds((const void *)&k_sp_move2<Word, DIR, P, FIX, HS>, lds);
+    int rc = allow_lds((const void *)&k_sp_move2<Word, DIR, P, FIX, HS, PAIR12>, lds);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_sp_move2<Word, DIR, P, FIX, HS>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
+    hipLaunchKernelGGL((k_sp_move2<Word, DIR, P, FIX, HS, PAIR12>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
                        ds.pa_run0, ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
                        (Word *)scratch, W, (int)tile, hs.maxrun, fx, ha, bs);
     return SF_OK;
   }
   const int run_cap = tile + runs + hot_static <= kMoveLdsOne ? hs.maxrun : 0;
   const size_t lds = tile + (run_cap ? runs : 0);
-  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX, HS>, lds);
+  int rc = allow_lds((const void *)&k_sp_move<Word, DIR, P, FIX, HS, PAIR12>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_sp_move<Word, DIR, P, FIX, HS>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
+  hipLaunchKernelGGL((k_sp_move<Word, DIR, P, FIX, HS, PAIR12>), dim3(g), dim3(kStageThreads), lds, st, ds.pa_loc,
                      ds.pa_run0, ds.pa_run, ds.tile_leaf0, ds.pa_slot, (int64_t)sf->nleaves, hs.ta, (Word *)leaf,
                      (Word *)scratch, W, (int)tile, run_cap, fx, ha, bs);
   return SF_OK;
 }
-template <typename Word, int DIR, int FIX = 0, typename HS = HotNone>
+template <typename Word, int DIR, int FIX = 0, typename HS = HotNone, bool PAIR12 = false>
 static int sp_move_w(sf_s *sf, int cls, void *leaf, void *scratch, int W, hipStream_t st, MoveFix fx = MoveFix{},
                      const HotArgs &ha = HotArgs{}, int bs = 1) {
   static_assert(kMoveTile == 8 * kStageThreads, "positions per thread");
   if (sf->hp.sp[cls].ta > kMoveTile) return SF_ERR_ARG;
-  return sp_move_p<Word, DIR, kMoveTile / kStageThreads, FIX, HS>(sf, cls, leaf, scratch, W, st, fx, ha, bs);
+  return sp_move_p<Word, DIR, kMoveTile / kStageThreads, FIX, HS, PAIR12>(sf, cls, leaf, scratch, W, st, fx, ha, bs);
 }
 
 static int sp_move(sf_s *sf, int cls, int dir, void *leaf, void *scratch, int64_t ub, hipStream_t st) {
@@ -1109,7 +1146,10 @@ int launch_reduce_part(sf_s *sf, const T *leaf, T *root, int bs, bool atomic, hi
       return sp_check();
     }
   }
-  rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
+  if constexpr (std::is_same<T, Pair>::value)  // pairs: 12-byte scratch units (16-byte aligned leaves)
+    rc = sp_move_w<uint4, 0, 0, HotNone, true>(sf, cls, (void *)leaf, scr, bs, st);
+  else
+    rc = sp_move(sf, cls, 0, (void *)leaf, scr, (int64_t)ub, st);
   if (rc) return rc;
   const unsigned gw = (unsigned)hs.win.size();
   if constexpr (kHasAtomic<OP>) {
