@@ -121,3 +121,60 @@ def test_partition_random_graph(case):
             else:
                 for c in range(fbs):
                     check_fetch_chain(g.iroot, slots, r0[:, c], lf[:, c], u[:, c], r[:, c])
+
+
+def _factors(rng, n, bs, dtype):
+    """PROD operands that keep long products finite and nonzero: signed
+    values near 1 (floating point), odd integers (integers)."""
+    shape = (n,) if bs == 1 else (n, bs)
+    if np.dtype(dtype).kind == "f":
+        return ((1.0 + 1e-3 * rng.standard_normal(shape)) * rng.choice([-1.0, 1.0], shape)).astype(dtype)
+    info = np.iinfo(dtype)
+    return rng.integers(info.min, info.max, size=shape, dtype=dtype, endpoint=True) | 1
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_graph_prod_minloc_half(case):
+    """The same random graphs: PROD (no native atomic: the deterministic
+    kernels in both modes, bit-exact), MINLOC with ties, and a binary16 /
+    bfloat16 SUM and MAX (direct kernels) -- each against the oracle."""
+    from helpers import BF16
+    g = random_graph(case)
+    rng = np.random.default_rng(9400 + case)
+    dtype, bs = UNITS[int(rng.integers(0, len(UNITS)))]
+    label = f"case {case}: nroots {g.nroots}, nleaves {g.nleaves}, {np.dtype(dtype)} x {bs}"
+    leaf = _factors(rng, g.leafspace, bs, dtype)
+    root = _factors(rng, g.nroots, bs, dtype)
+    want = oracle.reduce(g.nroots, g.iroot, g.ilocal, leaf, root, "prod")
+    for mode in ("deterministic", "atomic"):
+        def red(sf):
+            l, r = dev(leaf), dev(root)
+            sf.reduce(l, r, "prod", unit=unit(root))
+            return r
+        check(host(run(g, mode, red), root), want, f"{label}: prod {mode}")
+    lp = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    rp = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    want = oracle.reduce(g.nroots, g.iroot, g.ilocal, lp, rp, "minloc")
+    for mode in ("deterministic", "atomic"):
+        def red(sf):
+            l, r = dev(lp), dev(rp)
+            sf.reduce(l, r, "minloc", unit=unit(rp))
+            return r
+        check(host(run(g, mode, red), rp), want, f"{label}: minloc {mode}")
+    shape_l = (g.leafspace,) if bs == 1 else (g.leafspace, bs)
+    shape_r = (g.nroots,) if bs == 1 else (g.nroots, bs)
+    for fmt in ("f16", "bf16"):
+        xl, xr = rng.standard_normal(shape_l), rng.standard_normal(shape_r)
+        if fmt == "f16":
+            hl, hr = xl.astype(np.float16), xr.astype(np.float16)
+        else:
+            hl = (xl.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(BF16)
+            hr = (xr.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(BF16)
+        for op in ("sum", "max"):
+            want = oracle.reduce(g.nroots, g.iroot, g.ilocal, hl, hr, op)
+
+            def red(sf):
+                l, r = dev(hl), dev(hr)
+                sf.reduce(l, r, op, unit=unit(hr))
+                return r
+            check(host(run(g, "atomic", red), hr), want, f"{label}: {fmt} {op}")
