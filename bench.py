@@ -15,7 +15,7 @@ per distinct touched root) / measured time of a step, in GB/s.
 Unless ``--no-rows`` is given, more is measured after the timed loop and
 reported beside it: each op after a cache-evicting write, a device copy
 ceiling, the direct atomic kernels (partitioning off), the 3-D halo pattern
-path vs the generic index path, the batched persistent launch vs per-SF
+path vs the generic index path, the batched single launch vs per-SF
 launches (eager and graph-replayed), and the differentiable gather/scatter
 chain.  ``--profile-op NAME`` runs single ops (for rocprofv3 counters).
 """
@@ -500,22 +500,22 @@ def batch_row(torch, S, inputs, steps):
     res = {}
     with torch.cuda.stream(stream):
         batch.graph_capture(0, stream)
-        res_graph_persist = Op("graph_persistent", lambda: batch.graph_launch(stream), nbytes, "")
+        res_graph_persist = Op("graph_one_launch", lambda: batch.graph_launch(stream), nbytes, "")
         torch.cuda.synchronize()
-        for name, fn in (("persistent", lambda: batch.launch(stream)),
+        for name, fn in (("one_launch", lambda: batch.launch(stream)),
                          ("separate", lambda: batch.launch_separate(stream))):
             op = Op(name, fn, nbytes, "")
             time_ops(torch, [op], steps, 3)
             res[name] = op
         time_ops(torch, [res_graph_persist], steps, 3)
-        res["graph_persistent"] = res_graph_persist
+        res["graph_one_launch"] = res_graph_persist
         batch.graph_capture(1, stream)
         op = Op("graph_separate", lambda: batch.graph_launch(stream), nbytes, "")
         time_ops(torch, [op], steps, 3)
         res["graph_separate"] = op
     # host wall time of one launch-to-sync, median over reps
     wall = {}
-    for name, fn in (("persistent", lambda: batch.launch(stream)), ("separate", lambda: batch.launch_separate(stream))):
+    for name, fn in (("one_launch", lambda: batch.launch(stream)), ("separate", lambda: batch.launch_separate(stream))):
         ts = []
         for _ in range(10):
             t0 = time.perf_counter()
