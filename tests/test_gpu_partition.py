@@ -372,3 +372,48 @@ def test_partition_graph_capture(zipf, mode):
         gr.replay()
         torch.cuda.synchronize()
         check_all(f"replay {rep}")
+
+
+def test_graph_capture_pairs_and_bcast(zipf):
+    """MAXLOC / MINLOC through the partitioned path (12-byte scratch units)
+    and Bcast REPLACE (two blocks per tile) captured into a HIP graph after
+    one eager call each; three replays, each after eager work that resets the
+    outputs and synchronises, each checked against the oracle."""
+    from helpers import PAIR
+    g = zipf
+    rng = np.random.default_rng(817)
+    sf = S.StarForest(g.nroots, g.iroot, None, g.ranks).setup(reduce_mode="deterministic", partition="on")
+    lp = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+    rp = inputs.maxloc_roots(rng, g.nroots, ties=True)
+    want_max = oracle.reduce(g.nroots, g.iroot, None, lp, rp, "maxloc")
+    want_min = oracle.reduce(g.nroots, g.iroot, None, lp, rp, "minloc")
+    root = rng.standard_normal(g.nroots)
+    want_b = oracle.bcast(g.nroots, g.iroot, None, root, np.zeros(g.leafspace), "replace")
+    dl, dr0, dmax, dmin = dev(lp), dev(rp), dev(rp), dev(rp)
+    db_root, db_leaf = dev(root), dev(np.zeros(g.leafspace))
+    up, u64 = S.SfUnit(S.SF_F64_I32, 1), S.SfUnit(S.SF_F64, 1)
+
+    def run():
+        sf.reduce(dl, dmax, "maxloc", unit=up)
+        sf.reduce(dl, dmin, "minloc", unit=up)
+        sf.bcast(db_root, db_leaf, "replace", unit=u64)
+
+    def check_all(what):
+        check(host(dmax, rp), want_max, f"{what}: maxloc")
+        check(host(dmin, rp), want_min, f"{what}: minloc")
+        check(host(db_leaf, want_b), want_b, f"{what}: bcast")
+
+    run()
+    torch.cuda.synchronize()
+    check_all("eager")
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        run()
+    for rep in range(3):
+        dmax.copy_(dr0)
+        dmin.copy_(dr0)
+        db_leaf.zero_()
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        check_all(f"replay {rep}")
