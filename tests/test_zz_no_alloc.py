@@ -65,6 +65,22 @@ def test_noalloc_matches_reduce(mode, op, dtype):
         _same(got, oracle.reduce(g.nroots, g.iroot, None, leaf, root, op), f"call {k}: noalloc vs oracle")
 
 
+@pytest.mark.parametrize("mode,op", [("deterministic", "maxloc"), ("atomic", "minloc")])
+def test_noalloc_pairs(mode, op):
+    """MAXLOC / MINLOC pairs: the first call takes the partitioned path with
+    its 12-byte scratch units inside the fixed buffer."""
+    for k, (nr, nl) in enumerate(SIZES):
+        print(f"noalloc {mode} {op} nroots={nr} nleaves={nl}", flush=True)
+        g = inputs.spmv_ghost(seed=60 + k, nroots=nr, nleaves=nl)
+        rng = np.random.default_rng(930 + k)
+        leaf = inputs.maxloc_leaves(rng, g.leafspace, ties=True)
+        root = inputs.maxloc_roots(rng, g.nroots, ties=True)
+        got = _reduce(g, mode, leaf, root, op, True)
+        ref = _reduce(g, mode, leaf, root, op, False)
+        _same(got, ref, f"call {k}: noalloc vs sf_reduce_begin")
+        _same(got, oracle.reduce(g.nroots, g.iroot, None, leaf, root, op), f"call {k}: noalloc vs oracle")
+
+
 def test_noalloc_atomic_sum_f32():
     for k, (nr, nl) in enumerate(SIZES):
         print(f"noalloc atomic sum f32 nroots={nr} nleaves={nl}", flush=True)
