@@ -806,6 +806,22 @@ def test_half_bcast_and_replace(orc):
     assert got.tobytes() == want.tobytes()
 
 
+def test_omp_half_equals_sequential(orc):
+    g = inputs.spmv_ghost(seed=51, nroots=2000, nleaves=40001)
+    rng = np.random.default_rng(52)
+    for fmt in ("f16", "bf16"):
+        if fmt == "f16":
+            leaf = rng.standard_normal((g.nleaves, 2)).astype(np.float16)
+            root = rng.standard_normal((g.nroots, 2)).astype(np.float16)
+        else:
+            leaf = inputs.bf16_bits(rng, g.nleaves, 2).view(orc.BF16)
+            root = inputs.bf16_bits(rng, g.nroots, 2).view(orc.BF16)
+        for op in ("sum", "prod", "max", "min"):
+            a = orc.reduce(g.nroots, g.iroot, None, leaf, root, op)
+            b = orc.reduce_omp(g.nroots, g.iroot, None, leaf, root, op)
+            assert a.tobytes() == b.tobytes(), (fmt, op)
+
+
 # ------------------------------------------------ multi-SF, Gather, Scatter
 def test_fig2_gather_scatter(orc):
     """Fig. 2's multi-SF, Gather and Scatter against the values derived by
