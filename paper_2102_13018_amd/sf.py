@@ -460,7 +460,7 @@ def spmv_transpose(sf, At, Bt, x, lvec, y, stream=None):
 
 
 class Batch:
-    """A batch of SF operations run in one persistent launch (sf_batch_*).
+    """A batch of SF operations run in one kernel launch (sf_batch_*).
     items: list of (StarForest, unit, kind, op, root_tensor, leaf_tensor) or,
     for kind "fetch_and_op", (..., root, leaf, leafupdate)."""
 
